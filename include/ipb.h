@@ -1,0 +1,178 @@
+/*
+ * ipb.h - C ABI of the MI355X (gfx950) depth-completion library.
+ *
+ * The library fills a sparse float32 depth map with the eight-step classical
+ * pipeline of Ku, Harakeh & Waslander, "In Defense of Classical Image
+ * Processing: Fast Depth Completion on the CPU" (2018), Sec. III "Proposed
+ * Algorithm".  Problem statement (Sec. II, Eq. 1): given a sparse M x N depth
+ * map, return a dense map of the same size with empty pixels replaced by
+ * depth estimates; the method is unguided, so no image is taken.
+ *
+ * Stage numbers used by ipb_complete_stage():
+ *   1 depth inversion           (Sec. III "Depth Inversion")
+ *   2 kernel-shaped dilation    ("Custom Kernel Dilation")
+ *   3 closing                   ("Small Hole Closure")
+ *   4 small-hole fill           ("Small Hole Fill")
+ *   5 extension to the top      ("Extension to Top of Frame")
+ *   6 large-hole fill           ("Large Hole Fill")
+ *   7 median blur               ("Median and Gaussian Blur")
+ *   8 Gaussian blur             ("Median and Gaussian Blur")
+ *   9 output inversion          (the final "Depth Inversion")
+ * Stages 1-8 are in the inverted domain (valid = max_depth - depth, empty = 0);
+ * stage 9 is the output depth map (empty = 0).
+ *
+ * Conventions shared by every entry point:
+ *   - Maps are float32, row-major, pitch = W, in DEVICE memory.  1 <= H, W and
+ *     H * W < 2^31.
+ *   - Ownership: the caller owns every buffer (inputs, outputs, workspace) and
+ *     keeps it alive until the stream work completes.  The library keeps no
+ *     pointer after a call returns.
+ *   - Errors: every function returns an ipb_status and never aborts.  All
+ *     argument checks run before anything is enqueued: on error nothing is
+ *     enqueued and the outputs are untouched.  Faults during kernel execution
+ *     surface at the caller's next stream synchronisation, as with any HIP
+ *     launch.  The library never synchronises the stream.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Results are bitwise deterministic: the only atomic is an integer min.
+ */
+#ifndef IPB_H
+#define IPB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IPB_OK = 0,
+  IPB_ERR_INVALID_ARG = -1,   /* null pointer, bad size, bad parameter, overlap  */
+  IPB_ERR_UNSUPPORTED = -2,   /* a parameter value outside what the kernels hold */
+  IPB_ERR_WORKSPACE = -3,     /* workspace missing or smaller than required      */
+  IPB_ERR_HIP = -4            /* a HIP call failed; see ipb_last_hip_error()     */
+} ipb_status;
+
+/* Kernel shapes compared in Sec. IV "Custom Kernel Design" (Table 2).  The
+ * figure that draws them is not available; the shapes are read from their
+ * names: FULL all k x k, CROSS the centre row and column, DIAMOND
+ * |dx| + |dy| <= k/2, CIRCLE dx^2 + dy^2 <= (k/2)^2. */
+typedef enum { IPB_SE_FULL = 0, IPB_SE_CROSS = 1, IPB_SE_DIAMOND = 2, IPB_SE_CIRCLE = 3 } ipb_se;
+
+/* Pipeline parameters.  Defaults (ipb_params_default) are the paper's final
+ * design.  Supported values are listed per field; anything else returns
+ * IPB_ERR_UNSUPPORTED. */
+typedef struct {
+  uint32_t struct_size;     /* = sizeof(ipb_params); set by ipb_params_default    */
+  int32_t dilate_shape;     /* ipb_se; DIAMOND (Sec. III, Table 2)                 */
+  int32_t dilate_size;      /* 3, 5 or 7; 5 (Sec. IV "Custom Kernel Design")       */
+  int32_t close_size;       /* full kernel, 3, 5 or 7; 5 ("Small Hole Closure")    */
+  int32_t fill_size;        /* full kernel, 3, 5 or 7; 7 ("Small Hole Fill")       */
+  int32_t extrapolate;      /* 1: run stages 5 and 6; 0: skip both (the point-cloud
+                               use described in Sec. IV)                           */
+  int32_t large_fill_size;  /* full kernel, odd 3..31; 31 ("Large Hole Fill")      */
+  int32_t median_size;      /* 0 (off), 3 or 5; 5 ("Median and Gaussian Blur")     */
+  int32_t gauss_size;       /* 0 (off), 3 or 5; 5                                  */
+  float gauss_sigma;        /* <= 0: binomial taps (1 4 6 4 1)/16 for size 5;
+                               > 0: exp(-i^2 / 2 sigma^2), normalised              */
+  float max_depth;          /* inversion offset, 100.0 (Sec. III "Depth Inversion");
+                               must exceed 2 * valid_thresh                        */
+  float valid_thresh;       /* a value is empty iff <= this; 0.1; > 0              */
+  int32_t tile_local;       /* tile shape id for stages 1-4; 0 = automatic         */
+  int32_t tile_global;      /* tile shape id for stages 5-9; 0 = automatic         */
+} ipb_params;
+
+/* Fill *p with the paper's defaults (Sec. III; Tables 2 and 3: diamond 5x5
+ * dilation, 5x5 closing, 7x7 fill, extension, 31x31 fill, 5x5 median, 5x5
+ * Gaussian, offset 100).  p must not be NULL. */
+void ipb_params_default(ipb_params* p);
+
+/* Workspace bytes one frame of H x W needs (the stage-4 map and one int32 per
+ * column).  Returns 0 for invalid sizes. */
+size_t ipb_workspace_bytes(int H, int W, const ipb_params* p);
+
+/* Complete one frame: depth_in (H x W, device) -> depth_out (H x W, device).
+ * The whole chain of Sec. III, stages 1-9.  The workspace is taken from the
+ * stream-ordered allocator (hipMallocAsync) and released on the stream.
+ * depth_out == depth_in (in place) is allowed; any other overlap is
+ * IPB_ERR_INVALID_ARG. */
+int ipb_complete(const float* depth_in, int H, int W, const ipb_params* p,
+                 float* depth_out, void* stream);
+
+/* As ipb_complete with a caller-supplied device workspace of at least
+ * ipb_workspace_bytes(H, W, p) bytes (256-byte aligned).  Allocates nothing,
+ * synchronises nothing. */
+int ipb_complete_ws(const float* depth_in, int H, int W, const ipb_params* p,
+                    float* depth_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Test hook: run stages 1..last_stage (1 <= last_stage <= 9) and write the map
+ * of stage last_stage to out (see the stage list above).  Same workspace rule
+ * as ipb_complete_ws. */
+int ipb_complete_stage(const float* depth_in, int H, int W, const ipb_params* p,
+                       float* out, int last_stage, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- batches --
+ * Many frames of any sizes in one launch per phase.  Frames are independent
+ * (Sec. II: the map is completed from its own points only). */
+typedef struct {
+  const float* in;          /* device, H x W                                      */
+  float* out;               /* device, H x W; may equal in; frames must not overlap
+                               each other                                          */
+  int32_t H, W;
+} ipb_frame;
+
+/* Workspace for a batch: a descriptor table, the stage-4 maps and the column
+ * tables of all frames.  Returns 0 if any frame is invalid or n < 1. */
+size_t ipb_batch_workspace_bytes(const ipb_frame* frames, int n, const ipb_params* p);
+
+/* Complete n frames (host array of descriptors with device pointers).  The
+ * descriptor table is copied into the workspace with hipMemcpyAsync from the
+ * caller's host array, which may be reused as soon as the call returns. */
+int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of the launch plan for n frames (host side and device side alike). */
+size_t ipb_batch_plan_bytes(int n);
+
+/* Build, in host memory plan_host (ipb_batch_plan_bytes(n) bytes), the launch
+ * plan of n frames whose workspace will be ws (device, ws_bytes).  The plan
+ * holds device pointers into ws.  The caller copies it to device memory
+ * (plan_dev) and passes that to ipb_complete_planned; with a pinned plan
+ * buffer and a captured copy, a graph can be replayed for new frames (up to
+ * the sizes the workspace was sized for) by rewriting the host plan. */
+int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p,
+                   void* ws, size_t ws_bytes, void* plan_host, size_t plan_bytes);
+
+/* Run a planned batch.  plan_dev: device copy of a plan built by
+ * ipb_batch_plan; max_frames, max_tiles_local/global and max_cols bound the
+ * plans it may be replayed with (the launch grid is derived from them, so the
+ * call can be captured once and replayed).  phase: -1 = all phases; 0 = only
+ * the column-table reset; 1 = only stages 1-4; 2 = only stages 5-9 (phases
+ * must run in order 0, 1, 2; the split exists for per-kernel timing).
+ * Allocates nothing, synchronises nothing, reads no device memory on the host. */
+int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase,
+                         int max_tiles_local, int max_tiles_global, int max_cols,
+                         void* stream);
+
+/* Totals of a host plan: tiles per phase and columns (for max_* above). */
+int ipb_plan_totals(const void* plan_host, int* n, int* tiles_local, int* tiles_global, int* cols);
+
+/* ------------------------------------------------------------------ misc -- */
+
+/* Static text of a status code. */
+const char* ipb_status_string(int status);
+
+/* The hipError_t behind the calling thread's last IPB_ERR_HIP (0 if none). */
+int ipb_last_hip_error(void);
+
+/* Tile shapes (rows, cols) of a tile id for phase 1 (local) or 2 (global);
+ * returns IPB_ERR_INVALID_ARG for an unknown id.  Id 0 = automatic. */
+int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols);
+
+/* Number of tile ids per phase (ids 1..count). */
+int ipb_tile_count(int phase);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPB_H */

@@ -1,0 +1,152 @@
+"""Python face of the library: torch supplies device memory and the current
+stream, the HIP kernels behind the C ABI do all of the completion.
+
+    out = complete(depth)                  # 2-D float32 tensor on the GPU
+    outs = complete_batch([d0, d1, ...])   # frames of any sizes, one launch per phase
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+SE_FULL, SE_CROSS, SE_DIAMOND, SE_CIRCLE = 0, 1, 2, 3
+N_STAGES = 9
+
+
+@dataclasses.dataclass
+class Params:
+    """Mirror of ipb_params; defaults are the paper's final design
+    (Sec. III; Tables 2 and 3)."""
+    dilate_shape: int = SE_DIAMOND
+    dilate_size: int = 5
+    close_size: int = 5
+    fill_size: int = 7
+    extrapolate: int = 1
+    large_fill_size: int = 31
+    median_size: int = 5
+    gauss_size: int = 5
+    gauss_sigma: float = 0.0
+    max_depth: float = 100.0
+    valid_thresh: float = 0.1
+    tile_local: int = 0
+    tile_global: int = 0
+
+    def to_c(self) -> L.CParams:
+        c = L.CParams()
+        L.lib().ipb_params_default(ctypes.byref(c))
+        for f in dataclasses.fields(self):
+            setattr(c, f.name, getattr(self, f.name))
+        return c
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_map(t: torch.Tensor, name: str) -> None:
+    if not isinstance(t, torch.Tensor) or t.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D tensor")
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on the GPU")
+
+
+def _workspace(nbytes: int, device: torch.device) -> torch.Tensor:
+    # 256-byte aligned device workspace from torch's allocator
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    shift = (-buf.data_ptr()) % 256
+    return buf[shift:shift + nbytes]
+
+
+def workspace_bytes(H: int, W: int, params: Optional[Params] = None) -> int:
+    p = (params or Params()).to_c()
+    return int(L.lib().ipb_workspace_bytes(H, W, ctypes.byref(p)))
+
+
+def complete(depth: torch.Tensor, params: Optional[Params] = None, out: Optional[torch.Tensor] = None,
+             stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Dense map of one sparse H x W depth map (ipb_complete_ws)."""
+    return complete_stage(depth, N_STAGES, params, out, stream)
+
+
+def complete_stage(depth: torch.Tensor, last_stage: int, params: Optional[Params] = None,
+                   out: Optional[torch.Tensor] = None,
+                   stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Map after stage `last_stage` (1..9; stages 1-8 in the inverted domain)."""
+    _check_map(depth, "depth")
+    H, W = depth.shape
+    if out is None:
+        out = torch.empty_like(depth)
+    _check_map(out, "out")
+    p = (params or Params()).to_c()
+    nb = int(L.lib().ipb_workspace_bytes(H, W, ctypes.byref(p)))
+    if nb == 0:
+        L.check(L.IPB_ERR_INVALID_ARG, "ipb_workspace_bytes")
+    ws = _workspace(nb, depth.device)
+    st = L.lib().ipb_complete_stage(ctypes.c_void_p(depth.data_ptr()), H, W, ctypes.byref(p),
+                                    ctypes.c_void_p(out.data_ptr()), last_stage,
+                                    ctypes.c_void_p(ws.data_ptr()), nb, _stream_handle(stream))
+    L.check(st, "ipb_complete_stage")
+    return out
+
+
+def complete_alloc(depth: torch.Tensor, params: Optional[Params] = None, out: Optional[torch.Tensor] = None,
+                   stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """As complete(), with the library's own stream-ordered workspace
+    (ipb_complete)."""
+    _check_map(depth, "depth")
+    H, W = depth.shape
+    if out is None:
+        out = torch.empty_like(depth)
+    _check_map(out, "out")
+    p = (params or Params()).to_c()
+    st = L.lib().ipb_complete(ctypes.c_void_p(depth.data_ptr()), H, W, ctypes.byref(p),
+                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    L.check(st, "ipb_complete")
+    return out
+
+
+def frames_array(ins: Sequence[torch.Tensor], outs: Sequence[torch.Tensor]):
+    arr = (L.CFrame * len(ins))()
+    for i, (a, b) in enumerate(zip(ins, outs)):
+        _check_map(a, f"frames[{i}]")
+        _check_map(b, f"outs[{i}]")
+        if a.shape != b.shape:
+            raise ValueError(f"frame {i}: output shape differs from input")
+        arr[i].in_ = a.data_ptr()
+        arr[i].out = b.data_ptr()
+        arr[i].H, arr[i].W = a.shape
+    return arr
+
+
+def batch_workspace_bytes(frames: Sequence[torch.Tensor], params: Optional[Params] = None,
+                          outs: Optional[Sequence[torch.Tensor]] = None) -> int:
+    outs = list(outs) if outs is not None else list(frames)
+    arr = frames_array(frames, outs)
+    p = (params or Params()).to_c()
+    return int(L.lib().ipb_batch_workspace_bytes(arr, len(frames), ctypes.byref(p)))
+
+
+def complete_batch(frames: Sequence[torch.Tensor], params: Optional[Params] = None,
+                   outs: Optional[Sequence[torch.Tensor]] = None,
+                   stream: Optional[torch.cuda.Stream] = None) -> List[torch.Tensor]:
+    """Complete frames of any sizes together (ipb_complete_batch)."""
+    frames = list(frames)
+    if not frames:
+        return []
+    outs = list(outs) if outs is not None else [torch.empty_like(f) for f in frames]
+    arr = frames_array(frames, outs)
+    p = (params or Params()).to_c()
+    nb = int(L.lib().ipb_batch_workspace_bytes(arr, len(frames), ctypes.byref(p)))
+    if nb == 0:
+        L.check(L.IPB_ERR_INVALID_ARG, "ipb_batch_workspace_bytes")
+    ws = _workspace(nb, frames[0].device)
+    st = L.lib().ipb_complete_batch(arr, len(frames), ctypes.byref(p), ctypes.c_void_p(ws.data_ptr()), nb,
+                                    _stream_handle(stream))
+    L.check(st, "ipb_complete_batch")
+    return outs

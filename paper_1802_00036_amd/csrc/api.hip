@@ -1,0 +1,511 @@
+// Host side of the C ABI declared in include/ipb.h: argument checks,
+// workspace layout, launch plans and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "ipb.h"
+
+using namespace ipb;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = static_cast<int>(e);
+  return IPB_ERR_HIP;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool size_ok(int H, int W) {
+  return H >= 1 && W >= 1 && static_cast<long long>(H) * W < (1LL << 31);
+}
+
+// Parameters resolved into what the kernels take.
+struct Resolved {
+  KParams kp;
+  int ltile, gtile, halo;
+  int lth, ltw, gth, gtw;
+};
+
+bool odd_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v % 2) == 1; }
+
+int resolve(const ipb_params* p, Resolved* r) {
+  if (p == nullptr || p->struct_size != sizeof(ipb_params)) return IPB_ERR_INVALID_ARG;
+  if (p->dilate_shape < IPB_SE_FULL || p->dilate_shape > IPB_SE_CIRCLE) return IPB_ERR_INVALID_ARG;
+  const int sizes[] = {p->dilate_size, p->close_size, p->fill_size, p->large_fill_size};
+  for (int s : sizes)
+    if (s < 1 || s % 2 == 0) return IPB_ERR_INVALID_ARG;
+  if (p->median_size < 0 || (p->median_size != 0 && p->median_size % 2 == 0)) return IPB_ERR_INVALID_ARG;
+  if (p->gauss_size < 0 || (p->gauss_size != 0 && p->gauss_size % 2 == 0)) return IPB_ERR_INVALID_ARG;
+  if (!std::isfinite(p->max_depth) || !std::isfinite(p->valid_thresh) || !std::isfinite(p->gauss_sigma))
+    return IPB_ERR_INVALID_ARG;
+  if (!(p->valid_thresh > 0.f) || !(p->max_depth > 2.f * p->valid_thresh)) return IPB_ERR_INVALID_ARG;
+  if (p->extrapolate != 0 && p->extrapolate != 1) return IPB_ERR_INVALID_ARG;
+  if (!odd_in(p->dilate_size, 3, 7) || !odd_in(p->close_size, 3, 7) || !odd_in(p->fill_size, 3, 7) ||
+      !odd_in(p->large_fill_size, 3, 31))
+    return IPB_ERR_UNSUPPORTED;
+  if (p->median_size != 0 && !odd_in(p->median_size, 3, 5)) return IPB_ERR_UNSUPPORTED;
+  if (p->gauss_size != 0 && !odd_in(p->gauss_size, 3, 5)) return IPB_ERR_UNSUPPORTED;
+  if (p->tile_local < 0 || p->tile_local > num_local_tiles()) return IPB_ERR_INVALID_ARG;
+  if (p->tile_global < 0 || p->tile_global > num_global_tiles()) return IPB_ERR_INVALID_ARG;
+
+  KParams& k = r->kp;
+  std::memset(&k, 0, sizeof(k));
+  k.shape = p->dilate_shape;
+  k.rd = p->dilate_size / 2;
+  k.rc = p->close_size / 2;
+  k.rf = p->fill_size / 2;
+  k.extrapolate = p->extrapolate;
+  k.rl = p->large_fill_size / 2;
+  k.rm = p->median_size / 2;
+  k.rg = p->gauss_size / 2;
+  k.off = p->max_depth;
+  k.thr = p->valid_thresh;
+  k.last_stage = 9;
+  if (k.rg > 0) {
+    if (p->gauss_sigma <= 0.f) {
+      // binomial taps, kept as integers; the sum is scaled once at the end
+      if (k.rg == 2) { k.gw[0] = 6; k.gw[1] = 4; k.gw[2] = 1; k.gscale = 1.0 / 256.0; }
+      else { k.gw[0] = 2; k.gw[1] = 1; k.gw[2] = 0; k.gscale = 1.0 / 16.0; }
+    } else {
+      const double s = static_cast<double>(p->gauss_sigma);
+      double w[5] = {0, 0, 0, 0, 0};
+      double sum = 0.0;
+      for (int i = -k.rg; i <= k.rg; ++i) w[i + 2] = std::exp(-(double)(i * i) / (2.0 * s * s));
+      for (int i = -k.rg; i <= k.rg; ++i) sum += w[i + 2];
+      for (int i = 0; i <= k.rg; ++i) k.gw[i] = w[i + 2] / sum;
+      k.gscale = 1.0;
+    }
+  }
+  const int need_local = k.rd + 2 * k.rc + k.rf;
+  r->halo = need_local <= 9 ? 9 : 12;
+  if (need_local > 12) return IPB_ERR_UNSUPPORTED;
+  if (k.rl + k.rm + k.rg > 19) return IPB_ERR_UNSUPPORTED;
+  r->ltile = p->tile_local ? p->tile_local : 1;
+  r->gtile = p->tile_global ? p->tile_global : 1;
+  r->lth = local_tile_rows(r->ltile);
+  r->ltw = local_tile_cols(r->ltile);
+  r->gth = global_tile_rows(r->gtile);
+  r->gtw = global_tile_cols(r->gtile);
+  return IPB_OK;
+}
+
+int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Per-device facts: CU count and resident workgroups per kernel variant.
+struct DeviceFacts {
+  int cus = 0;
+  int occ[3][8][2] = {};   // [phase][tile id][halo 9/12]
+};
+std::mutex g_dev_mu;
+DeviceFacts g_dev[64];
+
+int device_cus(int* out_dev) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= 64) return IPB_ERR_UNSUPPORTED;
+  *out_dev = dev;
+  std::lock_guard<std::mutex> g(g_dev_mu);
+  if (g_dev[dev].cus == 0) {
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    g_dev[dev].cus = cus > 0 ? cus : 1;
+  }
+  return IPB_OK;
+}
+
+int resident(int dev, int phase, int tile, int halo) {
+  std::lock_guard<std::mutex> g(g_dev_mu);
+  int& slot = g_dev[dev].occ[phase][tile][halo == 12 ? 1 : 0];
+  if (slot == 0) slot = max_resident_blocks(phase, tile, halo);
+  return slot;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+// Pinned staging slots for plans copied by ipb_complete_batch; a slot is
+// reused only after the copy that last read it has completed.
+struct StagingSlot {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+struct Staging {
+  std::mutex mu;
+  StagingSlot slot[4];
+  int next = 0;
+};
+Staging g_staging[64];
+
+// Fill a plan (host memory) for frames whose workspace is ws.
+void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, void* plan_host) {
+  auto* hdr = static_cast<PlanHeader*>(plan_host);
+  auto* fd = reinterpret_cast<FrameDesc*>(hdr + 1);
+  std::memset(hdr, 0, sizeof(PlanHeader));
+  char* base = static_cast<char*>(ws);
+  size_t off = align_up(sizeof(PlanHeader) + sizeof(FrameDesc) * (size_t)n);
+  long long cols = 0;
+  for (int i = 0; i < n; ++i) cols += frames[i].W;
+  auto* top_base = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(sizeof(int32_t) * (size_t)cols);
+  int lt = 0, gt = 0, col = 0;
+  for (int i = 0; i < n; ++i) {
+    const int H = frames[i].H, W = frames[i].W;
+    FrameDesc& d = fd[i];
+    std::memset(&d, 0, sizeof(d));
+    d.in = frames[i].in;
+    d.out = frames[i].out;
+    d.v4 = reinterpret_cast<float*>(base + off);
+    off += align_up(sizeof(float) * (size_t)H * W);
+    d.top = top_base + col;
+    d.H = H;
+    d.W = W;
+    d.lcols = cdiv(W, r.ltw);
+    d.gcols = cdiv(W, r.gtw);
+    d.ltile0 = lt;
+    d.gtile0 = gt;
+    lt += d.lcols * cdiv(H, r.lth);
+    gt += d.gcols * cdiv(H, r.gth);
+    col += W;
+  }
+  hdr->n = n;
+  hdr->ltiles = lt;
+  hdr->gtiles = gt;
+  hdr->ncols = col;
+  hdr->top_base = top_base;
+  hdr->lt_rows = r.lth;
+  hdr->lt_cols = r.ltw;
+  hdr->gt_rows = r.gth;
+  hdr->gt_cols = r.gtw;
+}
+
+size_t batch_bytes(const ipb_frame* frames, int n) {
+  size_t total = align_up(sizeof(PlanHeader) + sizeof(FrameDesc) * (size_t)n);
+  size_t cols = 0;
+  for (int i = 0; i < n; ++i) cols += (size_t)frames[i].W;
+  total += align_up(sizeof(int32_t) * cols);
+  for (int i = 0; i < n; ++i) total += align_up(sizeof(float) * (size_t)frames[i].H * frames[i].W);
+  return total;
+}
+
+// Frames valid, outputs disjoint from every other frame's buffers.
+int check_frames(const ipb_frame* frames, int n) {
+  if (frames == nullptr || n < 1) return IPB_ERR_INVALID_ARG;
+  struct Iv { const char* lo; const char* hi; int frame; int is_out; };
+  std::vector<Iv> iv;
+  iv.reserve(2 * (size_t)n);
+  long long cols = 0;
+  for (int i = 0; i < n; ++i) {
+    const ipb_frame& f = frames[i];
+    if (f.in == nullptr || f.out == nullptr || !size_ok(f.H, f.W)) return IPB_ERR_INVALID_ARG;
+    const size_t nb = sizeof(float) * (size_t)f.H * f.W;
+    const char* in = reinterpret_cast<const char*>(f.in);
+    const char* out = reinterpret_cast<const char*>(f.out);
+    if (in != out && overlaps(in, nb, out, nb)) return IPB_ERR_INVALID_ARG;
+    iv.push_back({in, in + nb, i, 0});
+    if (out != in) iv.push_back({out, out + nb, i, 1});
+    else iv.back().is_out = 1;   // in-place: the one interval is also an output
+    cols += f.W;
+  }
+  if (cols >= (1LL << 31)) return IPB_ERR_INVALID_ARG;
+  std::sort(iv.begin(), iv.end(), [](const Iv& a, const Iv& b) { return a.lo < b.lo; });
+  // Any two overlapping intervals of different frames where one is an output
+  // is a conflict (inputs may be shared read-only).
+  for (size_t a = 0; a < iv.size(); ++a) {
+    for (size_t b = a + 1; b < iv.size() && iv[b].lo < iv[a].hi; ++b) {
+      if (iv[a].frame != iv[b].frame && (iv[a].is_out || iv[b].is_out)) return IPB_ERR_INVALID_ARG;
+    }
+  }
+  return IPB_OK;
+}
+
+FrameSource single_source(const float* in, int H, int W, float* out, void* ws, const Resolved& r) {
+  FrameSource s;
+  std::memset(&s, 0, sizeof(s));
+  s.plan = nullptr;
+  FrameDesc& d = s.single;
+  d.in = in;
+  d.out = out;
+  d.v4 = static_cast<float*>(ws);
+  d.top = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + align_up(sizeof(float) * (size_t)H * W));
+  d.H = H;
+  d.W = W;
+  d.lcols = cdiv(W, r.ltw);
+  d.gcols = cdiv(W, r.gtw);
+  d.ltile0 = 0;
+  d.gtile0 = 0;
+  s.single_ltiles = d.lcols * cdiv(H, r.lth);
+  s.single_gtiles = d.gcols * cdiv(H, r.gth);
+  return s;
+}
+
+size_t frame_ws_bytes(int H, int W) {
+  return align_up(sizeof(float) * (size_t)H * W) + align_up(sizeof(int32_t) * (size_t)W);
+}
+
+int run_single(const float* in, int H, int W, const ipb_params* p, float* out, int last_stage, void* ws,
+               size_t ws_bytes, hipStream_t s) {
+  Resolved r;
+  int st = resolve(p, &r);
+  if (st != IPB_OK) return st;
+  if (in == nullptr || out == nullptr || !size_ok(H, W)) return IPB_ERR_INVALID_ARG;
+  if (last_stage < 1 || last_stage > 9) return IPB_ERR_INVALID_ARG;
+  const size_t nb = sizeof(float) * (size_t)H * W;
+  if (in != out && overlaps(in, nb, out, nb)) return IPB_ERR_INVALID_ARG;
+  if (in == out && last_stage <= 4) return IPB_ERR_INVALID_ARG;   // stage 1-4 maps race with the halo reads
+  if (ws == nullptr || ws_bytes < frame_ws_bytes(H, W) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+    return IPB_ERR_WORKSPACE;
+  if (overlaps(ws, frame_ws_bytes(H, W), in, nb) || overlaps(ws, frame_ws_bytes(H, W), out, nb))
+    return IPB_ERR_INVALID_ARG;
+  r.kp.last_stage = last_stage;
+  FrameSource src = single_source(in, H, W, out, ws, r);
+  hipError_t e;
+  if (last_stage >= 5) {
+    e = launch_reset(src, W, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  e = launch_local(src, r.kp, r.ltile, r.halo, src.single_ltiles, s);
+  if (e != hipSuccess) return hip_fail(e);
+  if (last_stage >= 5) {
+    e = launch_global(src, r.kp, r.gtile, src.single_gtiles, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return IPB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ipb_params_default(ipb_params* p) {
+  if (p == nullptr) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(ipb_params);
+  p->dilate_shape = IPB_SE_DIAMOND;
+  p->dilate_size = 5;
+  p->close_size = 5;
+  p->fill_size = 7;
+  p->extrapolate = 1;
+  p->large_fill_size = 31;
+  p->median_size = 5;
+  p->gauss_size = 5;
+  p->gauss_sigma = 0.f;
+  p->max_depth = 100.f;
+  p->valid_thresh = 0.1f;
+  p->tile_local = 0;
+  p->tile_global = 0;
+}
+
+size_t ipb_workspace_bytes(int H, int W, const ipb_params* p) {
+  Resolved r;
+  if (resolve(p, &r) != IPB_OK || !size_ok(H, W)) return 0;
+  return frame_ws_bytes(H, W);
+}
+
+int ipb_complete_ws(const float* depth_in, int H, int W, const ipb_params* p, float* depth_out, void* ws,
+                    size_t ws_bytes, void* stream) {
+  return run_single(depth_in, H, W, p, depth_out, 9, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int ipb_complete_stage(const float* depth_in, int H, int W, const ipb_params* p, float* out, int last_stage,
+                       void* ws, size_t ws_bytes, void* stream) {
+  return run_single(depth_in, H, W, p, out, last_stage, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int ipb_complete(const float* depth_in, int H, int W, const ipb_params* p, float* depth_out, void* stream) {
+  Resolved r;
+  int st = resolve(p, &r);
+  if (st != IPB_OK) return st;
+  if (depth_in == nullptr || depth_out == nullptr || !size_ok(H, W)) return IPB_ERR_INVALID_ARG;
+  const size_t nb = sizeof(float) * (size_t)H * W;
+  if (depth_in != depth_out && overlaps(depth_in, nb, depth_out, nb)) return IPB_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = frame_ws_bytes(H, W);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, need, s);
+  if (e != hipSuccess) return hip_fail(e);
+  st = run_single(depth_in, H, W, p, depth_out, 9, ws, need, s);
+  e = hipFreeAsync(ws, s);
+  if (st != IPB_OK) return st;
+  if (e != hipSuccess) return hip_fail(e);
+  return IPB_OK;
+}
+
+size_t ipb_batch_plan_bytes(int n) {
+  if (n < 1) return 0;
+  return sizeof(PlanHeader) + sizeof(FrameDesc) * (size_t)n;
+}
+
+size_t ipb_batch_workspace_bytes(const ipb_frame* frames, int n, const ipb_params* p) {
+  Resolved r;
+  if (resolve(p, &r) != IPB_OK || check_frames(frames, n) != IPB_OK) return 0;
+  return batch_bytes(frames, n);
+}
+
+int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p, void* ws, size_t ws_bytes,
+                   void* plan_host, size_t plan_bytes) {
+  Resolved r;
+  int st = resolve(p, &r);
+  if (st != IPB_OK) return st;
+  st = check_frames(frames, n);
+  if (st != IPB_OK) return st;
+  if (plan_host == nullptr || plan_bytes < ipb_batch_plan_bytes(n)) return IPB_ERR_INVALID_ARG;
+  if (ws == nullptr || ws_bytes < batch_bytes(frames, n) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+    return IPB_ERR_WORKSPACE;
+  for (int i = 0; i < n; ++i) {
+    const size_t nb = sizeof(float) * (size_t)frames[i].H * frames[i].W;
+    if (overlaps(ws, ws_bytes, frames[i].in, nb) || overlaps(ws, ws_bytes, frames[i].out, nb))
+      return IPB_ERR_INVALID_ARG;
+  }
+  build_plan(frames, n, r, ws, plan_host);
+  return IPB_OK;
+}
+
+int ipb_plan_totals(const void* plan_host, int* n, int* tiles_local, int* tiles_global, int* cols) {
+  if (plan_host == nullptr) return IPB_ERR_INVALID_ARG;
+  const auto* h = static_cast<const PlanHeader*>(plan_host);
+  if (n) *n = h->n;
+  if (tiles_local) *tiles_local = h->ltiles;
+  if (tiles_global) *tiles_global = h->gtiles;
+  if (cols) *cols = h->ncols;
+  return IPB_OK;
+}
+
+int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase, int max_tiles_local,
+                         int max_tiles_global, int max_cols, void* stream) {
+  Resolved r;
+  int st = resolve(p, &r);
+  if (st != IPB_OK) return st;
+  if (plan_dev == nullptr || phase < -1 || phase > 2) return IPB_ERR_INVALID_ARG;
+  if (max_tiles_local < 1 || max_tiles_global < 1 || max_cols < 1) return IPB_ERR_INVALID_ARG;
+  int dev = 0;
+  st = device_cus(&dev);
+  if (st != IPB_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FrameSource src;
+  std::memset(&src, 0, sizeof(src));
+  src.plan = static_cast<const PlanHeader*>(plan_dev);
+  const int cus = g_dev[dev].cus;
+  hipError_t e;
+  if (phase == -1 || phase == 0) {
+    e = launch_reset(src, max_cols, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (phase == -1 || phase == 1) {
+    const int grid = std::min(max_tiles_local, resident(dev, 1, r.ltile, r.halo) * cus);
+    e = launch_local(src, r.kp, r.ltile, r.halo, grid, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (phase == -1 || phase == 2) {
+    const int grid = std::min(max_tiles_global, resident(dev, 2, r.gtile, 0) * cus);
+    e = launch_global(src, r.kp, r.gtile, grid, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return IPB_OK;
+}
+
+int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p, void* ws, size_t ws_bytes,
+                       void* stream) {
+  Resolved r;
+  int st = resolve(p, &r);
+  if (st != IPB_OK) return st;
+  st = check_frames(frames, n);
+  if (st != IPB_OK) return st;
+  if (ws == nullptr || ws_bytes < batch_bytes(frames, n) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+    return IPB_ERR_WORKSPACE;
+  for (int i = 0; i < n; ++i) {
+    const size_t nb = sizeof(float) * (size_t)frames[i].H * frames[i].W;
+    if (overlaps(ws, ws_bytes, frames[i].in, nb) || overlaps(ws, ws_bytes, frames[i].out, nb))
+      return IPB_ERR_INVALID_ARG;
+  }
+  int dev = 0;
+  st = device_cus(&dev);
+  if (st != IPB_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t pb = ipb_batch_plan_bytes(n);
+
+  Staging& stg = g_staging[dev];
+  std::lock_guard<std::mutex> g(stg.mu);
+  StagingSlot& slot = stg.slot[stg.next];
+  stg.next = (stg.next + 1) % 4;
+  hipError_t e;
+  if (slot.pending) {
+    e = hipEventSynchronize(slot.ev);   // the copy that last read this slot
+    if (e != hipSuccess) return hip_fail(e);
+    slot.pending = false;
+  }
+  if (slot.ev == nullptr) {
+    e = hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (slot.cap < pb) {
+    if (slot.host) (void)hipHostFree(slot.host);
+    slot.host = nullptr;
+    slot.cap = 0;
+    e = hipHostMalloc(&slot.host, pb, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e);
+    slot.cap = pb;
+  }
+  build_plan(frames, n, r, ws, slot.host);
+  const auto* hdr = static_cast<const PlanHeader*>(slot.host);
+  const int lt = hdr->ltiles, gt = hdr->gtiles, cols = hdr->ncols;
+  e = hipMemcpyAsync(ws, slot.host, pb, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e);
+  e = hipEventRecord(slot.ev, s);
+  if (e != hipSuccess) return hip_fail(e);
+  slot.pending = true;
+  return ipb_complete_planned(ws, p, -1, lt, gt, cols, stream);
+}
+
+const char* ipb_status_string(int status) {
+  switch (status) {
+    case IPB_OK: return "ok";
+    case IPB_ERR_INVALID_ARG: return "invalid argument";
+    case IPB_ERR_UNSUPPORTED: return "unsupported parameter value";
+    case IPB_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case IPB_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int ipb_last_hip_error(void) { return g_last_hip; }
+
+int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols) {
+  if (rows == nullptr || cols == nullptr) return IPB_ERR_INVALID_ARG;
+  if (tile_id == 0) tile_id = 1;
+  if (phase == 1 && tile_id >= 1 && tile_id <= num_local_tiles()) {
+    *rows = local_tile_rows(tile_id);
+    *cols = local_tile_cols(tile_id);
+    return IPB_OK;
+  }
+  if (phase == 2 && tile_id >= 1 && tile_id <= num_global_tiles()) {
+    *rows = global_tile_rows(tile_id);
+    *cols = global_tile_cols(tile_id);
+    return IPB_OK;
+  }
+  return IPB_ERR_INVALID_ARG;
+}
+
+int ipb_tile_count(int phase) {
+  if (phase == 1) return num_local_tiles();
+  if (phase == 2) return num_global_tiles();
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Shared device/host definitions of the gfx950 depth-completion library.
+//
+// Two phases per frame (the column extension of Sec. III "Extension to Top
+// of Frame" makes row 0 of a column depend on the lowest rows, so the chain
+// is split where that global dependency sits):
+//   phase 1 (local):  stages 1-4 on LDS tiles with a halo; writes the stage-4
+//                     map and, per column, the topmost non-empty row (atomic
+//                     integer min);
+//   phase 2 (global): stages 5-9 on LDS tiles with a halo; reads the stage-4
+//                     map and the column table, writes the output.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ipb {
+
+constexpr int kThreads = 256;          // 4 wave64 per workgroup
+constexpr int kNoTop = 0x7fffffff;      // column without a non-empty pixel
+
+// One frame as the kernels see it.
+struct FrameDesc {
+  const float* in;
+  float* out;
+  float* v4;          // stage-4 map, H * W floats
+  int32_t* top;       // W entries
+  int32_t H, W;
+  int32_t ltile0;     // first phase-1 tile of this frame within the launch
+  int32_t gtile0;     // first phase-2 tile
+  int32_t lcols;      // phase-1 tiles per row of tiles
+  int32_t gcols;      // phase-2 tiles per row of tiles
+  int32_t pad0, pad1;
+};
+
+// Device-resident launch plan: header followed by n FrameDesc.
+struct PlanHeader {
+  int32_t n;
+  int32_t ltiles;     // total phase-1 tiles
+  int32_t gtiles;     // total phase-2 tiles
+  int32_t ncols;      // total column-table entries (sum of W)
+  int32_t* top_base;  // column tables of all frames, contiguous
+  int32_t lt_rows, lt_cols;   // phase-1 tile shape the plan was built for
+  int32_t gt_rows, gt_cols;   // phase-2 tile shape
+  int32_t pad[6];
+};
+static_assert(sizeof(PlanHeader) == 64, "plan header layout");
+static_assert(sizeof(FrameDesc) == 64, "frame descriptor layout");
+
+// Kernel parameters, passed by value.
+struct KParams {
+  int32_t shape;      // ipb_se
+  int32_t rd;         // dilation radius
+  int32_t rc;         // closing radius
+  int32_t rf;         // small fill radius
+  int32_t extrapolate;
+  int32_t rl;         // large fill radius
+  int32_t rm;         // median radius (0 = off)
+  int32_t rg;         // Gaussian radius (0 = off)
+  float off;          // inversion offset
+  float thr;          // empty iff value <= thr
+  int32_t last_stage; // 1..9
+  int32_t pad;
+  double gw[3];       // Gaussian taps: centre, +-1, +-2 (integers for the binomial case)
+  double gscale;      // applied to the 2-D sum (1/256 for binomial 5, 1/16 for 3)
+};
+
+// Where a launch finds its frames: a device plan, or one frame by value.
+struct FrameSource {
+  const PlanHeader* plan;   // nullptr: single frame
+  FrameDesc single;
+  int32_t single_ltiles;
+  int32_t single_gtiles;
+};
+
+// Host-side launchers (kernels.hip).
+hipError_t launch_reset(const FrameSource& src, int max_cols, hipStream_t s);
+hipError_t launch_local(const FrameSource& src, const KParams& kp, int tile_id, int halo,
+                        int grid, hipStream_t s);
+hipError_t launch_global(const FrameSource& src, const KParams& kp, int tile_id,
+                         int grid, hipStream_t s);
+int local_tile_rows(int tile_id);
+int local_tile_cols(int tile_id);
+int global_tile_rows(int tile_id);
+int global_tile_cols(int tile_id);
+int num_local_tiles();
+int num_global_tiles();
+int max_resident_blocks(int phase, int tile_id, int halo);
+
+}  // namespace ipb

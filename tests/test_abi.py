@@ -1,0 +1,187 @@
+"""The C ABI without a GPU: the library loads, exports what include/ipb.h
+declares, and every argument check answers before any HIP call.  Also the
+host-side launch plan and the median network (compiled for the host)."""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_1802_00036_amd import _lib as L
+from paper_1802_00036_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1802_00036_amd", "csrc")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="libipb.so not built")
+
+FAKE = 0x7f0000000000          # an aligned address no check dereferences
+
+
+def P(**kw):
+    return api.Params(**kw).to_c()
+
+
+def test_exports_every_declared_function():
+    h = ctypes.CDLL(L.LIB_PATH)
+    names = L.header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(h, n), n
+
+
+def test_params_default_is_the_paper_design():
+    c = L.CParams()
+    L.lib().ipb_params_default(ctypes.byref(c))
+    assert c.struct_size == ctypes.sizeof(L.CParams)
+    assert (c.dilate_shape, c.dilate_size, c.close_size, c.fill_size) == (2, 5, 5, 7)
+    assert (c.extrapolate, c.large_fill_size, c.median_size, c.gauss_size) == (1, 31, 5, 5)
+    assert c.max_depth == 100.0 and abs(c.valid_thresh - 0.1) < 1e-7 and c.gauss_sigma == 0.0
+
+
+def test_status_strings():
+    for st in (0, -1, -2, -3, -4, 7):
+        assert isinstance(L.status_string(st), str)
+
+
+def _ws_call(p, H=10, W=10, inp=FAKE, out=FAKE + (1 << 30), ws=FAKE + (2 << 30), nb=1 << 20, stage=9):
+    return L.lib().ipb_complete_stage(ctypes.c_void_p(inp), H, W, ctypes.byref(p), ctypes.c_void_p(out), stage,
+                                      ctypes.c_void_p(ws), nb, None)
+
+
+def test_argument_checks_return_before_any_gpu_call():
+    p = P()
+    assert _ws_call(p, inp=0) == L.IPB_ERR_INVALID_ARG
+    assert _ws_call(p, out=0) == L.IPB_ERR_INVALID_ARG
+    assert _ws_call(p, H=0) == L.IPB_ERR_INVALID_ARG
+    assert _ws_call(p, W=-3) == L.IPB_ERR_INVALID_ARG
+    assert _ws_call(p, H=1 << 16, W=1 << 15) == L.IPB_ERR_INVALID_ARG        # H * W >= 2^31
+    assert _ws_call(p, stage=0) == L.IPB_ERR_INVALID_ARG
+    assert _ws_call(p, stage=10) == L.IPB_ERR_INVALID_ARG
+    assert _ws_call(p, ws=0) == L.IPB_ERR_WORKSPACE
+    assert _ws_call(p, nb=16) == L.IPB_ERR_WORKSPACE
+    assert _ws_call(p, ws=FAKE + (2 << 30) + 4) == L.IPB_ERR_WORKSPACE     # misaligned
+    assert _ws_call(p, out=FAKE + 8) == L.IPB_ERR_INVALID_ARG                # partial overlap
+    assert _ws_call(p, out=FAKE, stage=3) == L.IPB_ERR_INVALID_ARG           # in place, early stage
+    assert _ws_call(p, ws=FAKE + 256) == L.IPB_ERR_INVALID_ARG              # workspace over the input
+    bad = [dict(dilate_shape=7), dict(dilate_size=4), dict(dilate_size=-1), dict(median_size=2),
+           dict(valid_thresh=0.0), dict(max_depth=float("nan")), dict(max_depth=0.1), dict(extrapolate=2),
+           dict(tile_local=99), dict(tile_global=-1)]
+    for kw in bad:
+        assert _ws_call(P(**kw)) == L.IPB_ERR_INVALID_ARG, kw
+    unsupported = [dict(dilate_size=9), dict(close_size=9), dict(large_fill_size=33), dict(median_size=7),
+                   dict(gauss_size=7)]
+    for kw in unsupported:
+        assert _ws_call(P(**kw)) == L.IPB_ERR_UNSUPPORTED, kw
+    c = P()
+    c.struct_size = 4
+    assert _ws_call(c) == L.IPB_ERR_INVALID_ARG
+    assert L.lib().ipb_complete(None, 4, 4, ctypes.byref(p), None, None) == L.IPB_ERR_INVALID_ARG
+    assert L.lib().ipb_complete_ws(ctypes.c_void_p(FAKE), 4, 4, None, ctypes.c_void_p(FAKE + 4096),
+                                   ctypes.c_void_p(FAKE + 8192), 1 << 20, None) == L.IPB_ERR_INVALID_ARG
+
+
+def test_workspace_sizes():
+    p = P()
+    H, W = 375, 1242
+    nb = L.lib().ipb_workspace_bytes(H, W, ctypes.byref(p))
+    assert nb >= 4 * H * W + 4 * W and nb % 256 == 0
+    assert L.lib().ipb_workspace_bytes(0, 5, ctypes.byref(p)) == 0
+    assert L.lib().ipb_workspace_bytes(5, 5, None) == 0
+
+
+def _frames(shapes, base=FAKE, gap=1 << 28):
+    arr = (L.CFrame * len(shapes))()
+    for i, (H, W) in enumerate(shapes):
+        arr[i].in_ = base + 2 * i * gap
+        arr[i].out = base + (2 * i + 1) * gap
+        arr[i].H, arr[i].W = H, W
+    return arr
+
+
+def test_batch_plan_layout():
+    lib = L.lib()
+    p = P()
+    shapes = [(375, 1242), (1, 1), (300, 65), (512, 2048)]
+    arr = _frames(shapes)
+    nb = lib.ipb_batch_workspace_bytes(arr, len(shapes), ctypes.byref(p))
+    assert nb > sum(4 * h * w for h, w in shapes)
+    pb = lib.ipb_batch_plan_bytes(len(shapes))
+    plan = ctypes.create_string_buffer(pb)
+    ws = FAKE + (1 << 40)
+    assert lib.ipb_batch_plan(arr, len(shapes), ctypes.byref(p), ctypes.c_void_p(ws), nb, plan, pb) == 0
+    n, lt, gt, cols = (ctypes.c_int() for _ in range(4))
+    assert lib.ipb_plan_totals(plan, ctypes.byref(n), ctypes.byref(lt), ctypes.byref(gt), ctypes.byref(cols)) == 0
+    rows, ccols = ctypes.c_int(), ctypes.c_int()
+    lib.ipb_tile_shape(1, 0, ctypes.byref(rows), ctypes.byref(ccols))
+    want_lt = sum(-(-h // rows.value) * -(-w // ccols.value) for h, w in shapes)
+    lib.ipb_tile_shape(2, 0, ctypes.byref(rows), ctypes.byref(ccols))
+    want_gt = sum(-(-h // rows.value) * -(-w // ccols.value) for h, w in shapes)
+    assert (n.value, lt.value, gt.value, cols.value) == (4, want_lt, want_gt, sum(w for _, w in shapes))
+    # frame descriptors: 64-byte header then 64 bytes per frame
+    raw = np.frombuffer(plan.raw, dtype=np.uint8)
+    desc = raw[64:].reshape(len(shapes), 64)
+    ptrs = desc[:, :32].copy().view(np.uint64)          # in, out, v4, top
+    hw = desc[:, 32:48].copy().view(np.int32)            # H, W, ltile0, gtile0
+    for i, (H, W) in enumerate(shapes):
+        assert ptrs[i, 0] == arr[i].in_ and ptrs[i, 1] == arr[i].out
+        assert ptrs[i, 2] % 256 == 0 and ws <= ptrs[i, 2] < ws + nb
+        assert ptrs[i, 2] + 4 * H * W <= ws + nb
+        assert (hw[i, 0], hw[i, 1]) == (H, W)
+    # small workspace, overlapping outputs
+    assert lib.ipb_batch_plan(arr, 4, ctypes.byref(p), ctypes.c_void_p(ws), nb - 256, plan, pb) == L.IPB_ERR_WORKSPACE
+    arr2 = _frames([(10, 10), (10, 10)])
+    arr2[1].out = arr2[0].out + 16
+    assert lib.ipb_batch_workspace_bytes(arr2, 2, ctypes.byref(p)) == 0
+    arr3 = _frames([(10, 10), (10, 10)])
+    arr3[1].in_ = arr3[0].in_                            # a shared read-only input is allowed
+    assert lib.ipb_batch_workspace_bytes(arr3, 2, ctypes.byref(p)) > 0
+    arr4 = _frames([(10, 10)])
+    arr4[0].out = arr4[0].in_                            # in place
+    assert lib.ipb_batch_workspace_bytes(arr4, 1, ctypes.byref(p)) > 0
+    assert lib.ipb_complete_planned(None, ctypes.byref(p), -1, 1, 1, 1, None) == L.IPB_ERR_INVALID_ARG
+    assert lib.ipb_complete_planned(plan, ctypes.byref(p), 3, 1, 1, 1, None) == L.IPB_ERR_INVALID_ARG
+
+
+def test_tile_table():
+    lib = L.lib()
+    for phase in (1, 2):
+        n = lib.ipb_tile_count(phase)
+        assert n >= 4
+        for t in range(1, n + 1):
+            r, c = ctypes.c_int(), ctypes.c_int()
+            assert lib.ipb_tile_shape(phase, t, ctypes.byref(r), ctypes.byref(c)) == 0
+            assert r.value >= 8 and c.value >= 32
+        assert lib.ipb_tile_shape(phase, n + 1, ctypes.byref(ctypes.c_int()), ctypes.byref(ctypes.c_int())) != 0
+
+
+def test_median_network_on_host():
+    """The sorting network the median kernel uses, compiled for the CPU:
+    sorts, and its middle output is the median, for every window size used."""
+    src = r"""
+#include <cstdio>
+#include <cstdlib>
+#include <algorithm>
+#include "median_net.hpp"
+template <int N> int check(unsigned seed) {
+  float a[ipb::net::pow2_at_least(N)], b[N];
+  srand(seed);
+  for (int it = 0; it < 20000; ++it) {
+    for (int i = 0; i < N; ++i) { a[i] = b[i] = (float)(rand() % (it % 3 == 0 ? 4 : 1000)); }
+    ipb::net::sort_network<N>(a);
+    std::sort(b, b + N);
+    for (int i = 0; i < N; ++i) if (a[i] != b[i]) { printf("N=%d mismatch\n", N); return 1; }
+  }
+  return 0;
+}
+int main() { return check<9>(1) | check<25>(2) | check<13>(3) | check<7>(4); }
+"""
+    with tempfile.TemporaryDirectory() as d:
+        cpp = os.path.join(d, "t.cpp")
+        exe = os.path.join(d, "t")
+        with open(cpp, "w") as fh:
+            fh.write(src)
+        subprocess.run(["g++", "-O1", "-std=c++17", f"-I{CSRC}", cpp, "-o", exe], check=True)
+        assert subprocess.run([exe]).returncode == 0

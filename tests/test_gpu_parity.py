@@ -1,0 +1,203 @@
+"""GPU path (through the C ABI) against the CPU oracle, stage by stage.
+
+Bar: bit-exact on every stage for the default binomial Gaussian (the GPU sums
+the blur in float64, where the binomial sum is exact, so both sides round the
+same exact value once).  For sigma > 0 the blur taps are not dyadic, the sums
+are not exact and the order differs (separable on the GPU, 2-D in the
+oracle): stage 8 must then agree within 1e-5 relative and the output within
+1e-5 * v8 + one ulp of the output (output = max_depth - v8)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1802_00036_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def bits(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32)).view(np.uint32)
+
+
+def gpu_stage(m, k, p=None):
+    t = torch.from_numpy(np.ascontiguousarray(m, np.float32)).to(DEV)
+    out = api.complete_stage(t, k, p)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_params(p: api.Params) -> oracle.Params:
+    return oracle.Params(dilate_shape=p.dilate_shape, dilate_size=p.dilate_size, close_size=p.close_size,
+                         fill_size=p.fill_size, extrapolate=p.extrapolate, large_fill_size=p.large_fill_size,
+                         median_size=p.median_size, gauss_size=p.gauss_size, gauss_sigma=p.gauss_sigma,
+                         max_depth=p.max_depth, valid_thresh=p.valid_thresh)
+
+
+def assert_stage_equal(got, want, tag):
+    if np.array_equal(bits(got), bits(want)):
+        return
+    bad = np.argwhere(bits(got) != bits(want))
+    y, x = bad[0]
+    raise AssertionError(f"{tag}: {len(bad)} mismatches, first at ({y},{x}): gpu {got[y, x]!r} "
+                         f"oracle {want[y, x]!r}")
+
+
+def assert_all_stages(m, p=None, stages=range(1, 10), tag=""):
+    p = p or api.Params()
+    ref = oracle.complete(m, oracle_params(p))
+    for k in stages:
+        got = gpu_stage(m, k, p)
+        assert_stage_equal(got, ref[k - 1], f"{tag} {m.shape} stage {k}")
+
+
+# ---------------------------------------------------------------- sizes --
+
+EDGE = [1, 2, 3, 5, 8, 9, 17, 31, 32, 33, 63, 64, 65, 127, 129]
+
+
+@pytest.mark.parametrize("H", [1, 2, 3, 17, 32, 33, 65])
+def test_tile_edge_sizes(H):
+    rng = np.random.default_rng(H)
+    for W in EDGE:
+        m = synth.random_map(rng, H, W, 0.08, 1.0, 80.0)
+        print(f"[tile edge] {H}x{W}", flush=True)
+        assert_all_stages(m, tag="edge")
+
+
+@pytest.mark.parametrize("HW", [(375, 1242), (352, 1216), (129, 257), (200, 65), (31, 1000)])
+def test_lidar_frames_all_stages(HW):
+    H, W = HW
+    f = synth.lidar_frame(H, W, seed=[7, H, W], n_rows=min(64, H), density=0.05)
+    print(f"[lidar] {H}x{W}", flush=True)
+    assert_all_stages(f.sparse, tag="lidar")
+
+
+def test_workload_frames_full_size():
+    """Frames of the four workloads at their real sizes, full output."""
+    frames = [synth.config_frames(1)[0]] + synth.config_frames(2, limit=2) + synth.config_frames(3, limit=2) \
+        + synth.config_frames(4, limit=1)
+    for f in frames:
+        m = f.sparse
+        p = api.Params(max_depth=140.0 if f.max_depth > 80 else 100.0)
+        print(f"[workload] {m.shape}", flush=True)
+        ref = oracle.complete_map(m, oracle_params(p))
+        t = torch.from_numpy(m).to(DEV)
+        got = api.complete(t, p).cpu().numpy()
+        assert_stage_equal(got, ref, f"workload {m.shape}")
+
+
+# ----------------------------------------------------------- parameters --
+
+VARIANTS = [
+    api.Params(dilate_shape=api.SE_CROSS),
+    api.Params(dilate_shape=api.SE_FULL),
+    api.Params(dilate_shape=api.SE_CIRCLE),
+    api.Params(dilate_shape=api.SE_FULL, dilate_size=3),
+    api.Params(dilate_shape=api.SE_FULL, dilate_size=7),
+    api.Params(dilate_shape=api.SE_DIAMOND, dilate_size=7),
+    api.Params(dilate_shape=api.SE_CROSS, dilate_size=3, close_size=3, fill_size=5),
+    api.Params(close_size=7, fill_size=7, dilate_size=7),          # local halo 12
+    api.Params(extrapolate=0),
+    api.Params(median_size=0),
+    api.Params(gauss_size=0),
+    api.Params(median_size=0, gauss_size=0),
+    api.Params(median_size=3, gauss_size=3),
+    api.Params(large_fill_size=15),
+    api.Params(large_fill_size=3),
+    api.Params(max_depth=140.0),
+    api.Params(valid_thresh=0.5),
+]
+
+
+@pytest.mark.parametrize("i", range(len(VARIANTS)))
+def test_param_variants(i):
+    p = VARIANTS[i]
+    f = synth.lidar_frame(150, 300, seed=[11, i], n_rows=32, density=0.05)
+    print(f"[variant {i}] {p}", flush=True)
+    assert_all_stages(f.sparse, p, tag=f"variant {i}")
+    rng = np.random.default_rng(i)
+    assert_all_stages(synth.random_map(rng, 37, 70, 0.03, 1.0, 79.0), p, tag=f"variant {i} random")
+
+
+@pytest.mark.parametrize("tl", [1, 2, 3, 4])
+@pytest.mark.parametrize("tg", [1, 2, 3, 4])
+def test_tile_shapes(tl, tg):
+    p = api.Params(tile_local=tl, tile_global=tg)
+    f = synth.lidar_frame(133, 290, seed=[12, tl, tg], n_rows=40, density=0.05)
+    print(f"[tiles] local {tl} global {tg}", flush=True)
+    assert_all_stages(f.sparse, p, stages=(4, 5, 6, 7, 9), tag=f"tiles {tl}/{tg}")
+
+
+@pytest.mark.parametrize("sigma", [0.8, 1.1, 2.0])
+def test_gaussian_sigma_tolerance(sigma):
+    p = api.Params(gauss_sigma=sigma)
+    f = synth.lidar_frame(120, 260, seed=[13, int(sigma * 10)], n_rows=32, density=0.05)
+    m = f.sparse
+    ref = oracle.complete(m, oracle_params(p))
+    for k in range(1, 8):
+        assert_stage_equal(gpu_stage(m, k, p), ref[k - 1], f"sigma {sigma} stage {k}")
+    v8 = gpu_stage(m, 8, p)
+    r8 = ref[7]
+    assert np.array_equal(v8 > 0, r8 > 0)
+    assert np.all(np.abs(v8.astype(np.float64) - r8) <= 1e-5 * np.abs(r8.astype(np.float64)))
+    out = gpu_stage(m, 9, p)
+    r9 = ref[8]
+    ulp = np.spacing(np.abs(r9)).astype(np.float64)
+    assert np.all(np.abs(out.astype(np.float64) - r9) <= 1e-5 * r8.astype(np.float64) + ulp)
+
+
+# ------------------------------------------------------------ edge cases --
+
+def test_degenerate_maps():
+    for m in (np.zeros((40, 70), np.float32), np.full((40, 70), 12.5, np.float32),
+              np.full((1, 1), 30.0, np.float32), np.zeros((1, 1), np.float32)):
+        assert_all_stages(m, tag="degenerate")
+
+
+def test_special_values():
+    rng = np.random.default_rng(5)
+    m = synth.random_map(rng, 50, 90, 0.2, 1.0, 80.0)
+    specials = np.array([np.nan, np.inf, -np.inf, -3.0, -0.0, 0.05, 0.1, 99.9, 99.95, 100.0, 150.0,
+                         1e30, 1e-30, 0.1000001], np.float32)
+    idx = rng.choice(m.size, size=specials.size * 20, replace=False)
+    m.ravel()[idx] = np.tile(specials, 20)
+    assert_all_stages(m, tag="specials")
+
+
+def test_alloc_path_and_in_place():
+    f = synth.lidar_frame(200, 333, seed=[14], n_rows=48, density=0.05)
+    t = torch.from_numpy(f.sparse).to(DEV)
+    a = api.complete(t).cpu().numpy()
+    b = api.complete_alloc(t).cpu().numpy()
+    c = t.clone()
+    api.complete(c, out=c)
+    assert_stage_equal(b, a, "ipb_complete vs ipb_complete_ws")
+    assert_stage_equal(c.cpu().numpy(), a, "in place")
+
+
+def test_batch_equals_per_frame():
+    rng = np.random.default_rng(15)
+    maps = [synth.lidar_frame(int(rng.integers(20, 300)), int(rng.integers(20, 700)), seed=[15, i],
+                              n_rows=32, density=0.06).sparse for i in range(9)]
+    maps.append(np.zeros((5, 3), np.float32))
+    maps.append(synth.random_map(rng, 1, 1, 1.0))
+    ts = [torch.from_numpy(m).to(DEV) for m in maps]
+    singles = [api.complete(t).cpu().numpy() for t in ts]
+    for order in (list(range(len(ts))), list(reversed(range(len(ts))))):
+        outs = api.complete_batch([ts[i] for i in order])
+        for j, i in enumerate(order):
+            assert_stage_equal(outs[j].cpu().numpy(), singles[i], f"batch frame {i}")
+    for i, m in enumerate(maps[:4]):
+        assert_stage_equal(singles[i], oracle.complete_map(m), f"batch oracle {i}")
+
+
+def test_batch_uniform_workload_sample():
+    """A slice of the 64 x 375x1242 batch: batched output equals the oracle."""
+    frames = synth.config_frames(2, limit=6)
+    ts = [torch.from_numpy(f.sparse).to(DEV) for f in frames]
+    outs = api.complete_batch(ts)
+    for f, o in zip(frames, outs):
+        assert_stage_equal(o.cpu().numpy(), oracle.complete_map(f.sparse), "batch c2")
