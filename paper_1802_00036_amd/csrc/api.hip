@@ -34,7 +34,10 @@ struct Resolved {
   KParams kp;
   int ltile, gtile, halo;
   int lth, ltw, gth, gtw;
+  bool lstream, gstream;   // streaming kernels (tile ids 5-7) or LDS tile kernels (ids 1-4)
 };
+
+constexpr int kTileIds = 7;
 
 bool odd_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v % 2) == 1; }
 
@@ -55,8 +58,8 @@ int resolve(const ipb_params* p, Resolved* r) {
     return IPB_ERR_UNSUPPORTED;
   if (p->median_size != 0 && !odd_in(p->median_size, 3, 5)) return IPB_ERR_UNSUPPORTED;
   if (p->gauss_size != 0 && !odd_in(p->gauss_size, 3, 5)) return IPB_ERR_UNSUPPORTED;
-  if (p->tile_local < 0 || p->tile_local > num_local_tiles()) return IPB_ERR_INVALID_ARG;
-  if (p->tile_global < 0 || p->tile_global > num_global_tiles()) return IPB_ERR_INVALID_ARG;
+  if (p->tile_local < 0 || p->tile_local > kTileIds) return IPB_ERR_INVALID_ARG;
+  if (p->tile_global < 0 || p->tile_global > kTileIds) return IPB_ERR_INVALID_ARG;
 
   KParams& k = r->kp;
   std::memset(&k, 0, sizeof(k));
@@ -90,12 +93,27 @@ int resolve(const ipb_params* p, Resolved* r) {
   r->halo = need_local <= 9 ? 9 : 12;
   if (need_local > 12) return IPB_ERR_UNSUPPORTED;
   if (k.rl + k.rm + k.rg > 19) return IPB_ERR_UNSUPPORTED;
-  r->ltile = p->tile_local ? p->tile_local : 1;
-  r->gtile = p->tile_global ? p->tile_global : 1;
-  r->lth = local_tile_rows(r->ltile);
-  r->ltw = local_tile_cols(r->ltile);
-  r->gth = global_tile_rows(r->gtile);
-  r->gtw = global_tile_cols(r->gtile);
+  const bool ls_ok = stream_local_supported(k.shape, k.rd, k.rc, k.rf);
+  const bool gs_ok = stream_global_supported(k.rm, k.rg);
+  r->ltile = p->tile_local ? p->tile_local : (ls_ok ? 5 : 1);
+  r->gtile = p->tile_global ? p->tile_global : (gs_ok ? 5 : 1);
+  r->lstream = r->ltile >= 5;
+  r->gstream = r->gtile >= 5;
+  if ((r->lstream && !ls_ok) || (r->gstream && !gs_ok)) return IPB_ERR_UNSUPPORTED;
+  if (r->lstream) {
+    r->lth = stream_local_tile_rows(r->ltile);
+    r->ltw = stream_local_tile_cols(r->ltile);
+  } else {
+    r->lth = local_tile_rows(r->ltile);
+    r->ltw = local_tile_cols(r->ltile);
+  }
+  if (r->gstream) {
+    r->gth = stream_global_tile_rows(r->gtile);
+    r->gtw = stream_global_tile_cols(r->gtile);
+  } else {
+    r->gth = global_tile_rows(r->gtile);
+    r->gtw = global_tile_cols(r->gtile);
+  }
   return IPB_OK;
 }
 
@@ -104,7 +122,9 @@ int cdiv(int a, int b) { return (a + b - 1) / b; }
 // Per-device facts: CU count and resident workgroups per kernel variant.
 struct DeviceFacts {
   int cus = 0;
-  int occ[3][8][2] = {};   // [phase][tile id][halo 9/12]
+  int occ[3][8][2] = {};    // LDS kernels: [phase][tile id][halo 9/12]
+  int socc[3][8][16] = {};  // streaming kernels: [phase][tile id][shape * 4 + radius]
+  int slow_occ = 0;
 };
 std::mutex g_dev_mu;
 DeviceFacts g_dev[64];
@@ -129,6 +149,21 @@ int resident(int dev, int phase, int tile, int halo) {
   std::lock_guard<std::mutex> g(g_dev_mu);
   int& slot = g_dev[dev].occ[phase][tile][halo == 12 ? 1 : 0];
   if (slot == 0) slot = max_resident_blocks(phase, tile, halo);
+  return slot;
+}
+
+int stream_res(int dev, int phase, const Resolved& r) {
+  std::lock_guard<std::mutex> g(g_dev_mu);
+  const int key = phase == 1 ? (r.kp.shape * 4 + r.kp.rd) : 0;
+  int& slot = g_dev[dev].socc[phase][phase == 1 ? r.ltile : r.gtile][key];
+  if (slot == 0) slot = stream_resident_blocks(phase, phase == 1 ? r.ltile : r.gtile, r.kp);
+  return slot;
+}
+
+int slow_res(int dev) {
+  std::lock_guard<std::mutex> g(g_dev_mu);
+  int& slot = g_dev[dev].slow_occ;
+  if (slot == 0) slot = slow_resident_blocks();
   return slot;
 }
 
@@ -164,6 +199,10 @@ void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, voi
   for (int i = 0; i < n; ++i) cols += frames[i].W;
   auto* top_base = reinterpret_cast<int32_t*>(base + off);
   off += align_up(sizeof(int32_t) * (size_t)cols);
+  long long gtot = 0;
+  for (int i = 0; i < n; ++i) gtot += (long long)cdiv(frames[i].W, r.gtw) * cdiv(frames[i].H, r.gth);
+  auto* slow = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot));
   int lt = 0, gt = 0, col = 0;
   for (int i = 0; i < n; ++i) {
     const int H = frames[i].H, W = frames[i].W;
@@ -172,6 +211,8 @@ void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, voi
     d.in = frames[i].in;
     d.out = frames[i].out;
     d.v4 = reinterpret_cast<float*>(base + off);
+    off += align_up(sizeof(float) * (size_t)H * W);
+    d.v6p = reinterpret_cast<float*>(base + off);
     off += align_up(sizeof(float) * (size_t)H * W);
     d.top = top_base + col;
     d.H = H;
@@ -193,14 +234,18 @@ void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, voi
   hdr->lt_cols = r.ltw;
   hdr->gt_rows = r.gth;
   hdr->gt_cols = r.gtw;
+  hdr->slow = slow;
+  hdr->slow_cap = (int32_t)gtot;
 }
 
-size_t batch_bytes(const ipb_frame* frames, int n) {
+size_t batch_bytes(const ipb_frame* frames, int n, const Resolved& r) {
   size_t total = align_up(sizeof(PlanHeader) + sizeof(FrameDesc) * (size_t)n);
-  size_t cols = 0;
+  size_t cols = 0, gtot = 0;
   for (int i = 0; i < n; ++i) cols += (size_t)frames[i].W;
+  for (int i = 0; i < n; ++i) gtot += (size_t)cdiv(frames[i].W, r.gtw) * cdiv(frames[i].H, r.gth);
   total += align_up(sizeof(int32_t) * cols);
-  for (int i = 0; i < n; ++i) total += align_up(sizeof(float) * (size_t)frames[i].H * frames[i].W);
+  total += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot));
+  for (int i = 0; i < n; ++i) total += 2 * align_up(sizeof(float) * (size_t)frames[i].H * frames[i].W);
   return total;
 }
 
@@ -243,7 +288,10 @@ FrameSource single_source(const float* in, int H, int W, float* out, void* ws, c
   d.in = in;
   d.out = out;
   d.v4 = static_cast<float*>(ws);
-  d.top = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + align_up(sizeof(float) * (size_t)H * W));
+  const size_t map = align_up(sizeof(float) * (size_t)H * W);
+  d.v6p = reinterpret_cast<float*>(static_cast<char*>(ws) + map);
+  d.top = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 2 * map);
+  s.slow = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 2 * map + align_up(sizeof(int32_t) * (size_t)W));
   d.H = H;
   d.W = W;
   d.lcols = cdiv(W, r.ltw);
@@ -252,11 +300,60 @@ FrameSource single_source(const float* in, int H, int W, float* out, void* ws, c
   d.gtile0 = 0;
   s.single_ltiles = d.lcols * cdiv(H, r.lth);
   s.single_gtiles = d.gcols * cdiv(H, r.gth);
+  s.slow_cap = s.single_gtiles;
   return s;
 }
 
-size_t frame_ws_bytes(int H, int W) {
-  return align_up(sizeof(float) * (size_t)H * W) + align_up(sizeof(int32_t) * (size_t)W);
+size_t frame_ws_bytes(int H, int W, const Resolved& r) {
+  const size_t gtiles = (size_t)cdiv(W, r.gtw) * cdiv(H, r.gth);
+  return 2 * align_up(sizeof(float) * (size_t)H * W) + align_up(sizeof(int32_t) * (size_t)W) +
+         align_up(sizeof(int32_t) * slow_queue_ints((int)gtiles));
+}
+
+// Launch the phases of a frame source: 0 = reset, 1 = stages 1-4, 2 = stages 5-9.
+int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last_stage, int max_lt, int max_gt,
+                  int max_cols, bool persistent, hipStream_t s) {
+  int dev = 0;
+  int st = device_cus(&dev);
+  if (st != IPB_OK) return st;
+  const int cus = g_dev[dev].cus;
+  KParams kp = r.kp;
+  kp.last_stage = last_stage;
+  hipError_t e;
+  if ((phase == -1 || phase == 0) && last_stage >= 5) {
+    e = launch_reset(src, max_cols, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  // Streaming kernels: one wave per tile, a grid of every tile (rounded up to
+  // a multiple of the 8 XCDs); surplus blocks find no tile and exit.  LDS
+  // kernels of a planned launch: a persistent grid of resident blocks.
+  if (phase == -1 || phase == 1) {
+    int grid = max_lt;
+    if (r.lstream) grid = (grid + 7) / 8 * 8;
+    else if (persistent) grid = std::min(grid, resident(dev, 1, r.ltile, r.halo) * cus);
+    e = r.lstream ? launch_local_stream(src, kp, r.ltile, grid, s) : launch_local(src, kp, r.ltile, r.halo, grid, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if ((phase == -1 || phase == 2) && last_stage >= 5) {
+    int grid = max_gt;
+    if (r.gstream) grid = (grid + 7) / 8 * 8;
+    else if (persistent) grid = std::min(grid, resident(dev, 2, r.gtile, 0) * cus);
+    if (r.gstream) {
+      e = launch_global_stream(src, kp, r.gtile, grid, s);
+      if (e != hipSuccess) return hip_fail(e);
+      // queued quarters: at most four per tile; a grid of 32 waves per CU
+      const int rgrid = std::max(1, std::min(4 * max_gt, 32 * cus));
+      e = launch_global_repair(src, kp, r.gtile, rgrid, s);
+      if (e != hipSuccess) return hip_fail(e);
+      const int per = slow_subtiles(r.gth, r.gtw);
+      const int sgrid = std::max(1, std::min(max_gt * per, slow_res(dev) * cus));
+      e = launch_global_slow(src, kp, r.gth, r.gtw, sgrid, s);
+    } else {
+      e = launch_global(src, kp, r.gtile, grid, s);
+    }
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return IPB_OK;
 }
 
 int run_single(const float* in, int H, int W, const ipb_params* p, float* out, int last_stage, void* ws,
@@ -269,24 +366,12 @@ int run_single(const float* in, int H, int W, const ipb_params* p, float* out, i
   const size_t nb = sizeof(float) * (size_t)H * W;
   if (in != out && overlaps(in, nb, out, nb)) return IPB_ERR_INVALID_ARG;
   if (in == out && last_stage <= 4) return IPB_ERR_INVALID_ARG;   // stage 1-4 maps race with the halo reads
-  if (ws == nullptr || ws_bytes < frame_ws_bytes(H, W) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+  if (ws == nullptr || ws_bytes < frame_ws_bytes(H, W, r) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
     return IPB_ERR_WORKSPACE;
-  if (overlaps(ws, frame_ws_bytes(H, W), in, nb) || overlaps(ws, frame_ws_bytes(H, W), out, nb))
+  if (overlaps(ws, frame_ws_bytes(H, W, r), in, nb) || overlaps(ws, frame_ws_bytes(H, W, r), out, nb))
     return IPB_ERR_INVALID_ARG;
-  r.kp.last_stage = last_stage;
   FrameSource src = single_source(in, H, W, out, ws, r);
-  hipError_t e;
-  if (last_stage >= 5) {
-    e = launch_reset(src, W, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  e = launch_local(src, r.kp, r.ltile, r.halo, src.single_ltiles, s);
-  if (e != hipSuccess) return hip_fail(e);
-  if (last_stage >= 5) {
-    e = launch_global(src, r.kp, r.gtile, src.single_gtiles, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  return IPB_OK;
+  return launch_phases(src, r, -1, last_stage, src.single_ltiles, src.single_gtiles, W, false, s);
 }
 
 }  // namespace
@@ -315,7 +400,7 @@ void ipb_params_default(ipb_params* p) {
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p) {
   Resolved r;
   if (resolve(p, &r) != IPB_OK || !size_ok(H, W)) return 0;
-  return frame_ws_bytes(H, W);
+  return frame_ws_bytes(H, W, r);
 }
 
 int ipb_complete_ws(const float* depth_in, int H, int W, const ipb_params* p, float* depth_out, void* ws,
@@ -336,7 +421,7 @@ int ipb_complete(const float* depth_in, int H, int W, const ipb_params* p, float
   const size_t nb = sizeof(float) * (size_t)H * W;
   if (depth_in != depth_out && overlaps(depth_in, nb, depth_out, nb)) return IPB_ERR_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t need = frame_ws_bytes(H, W);
+  const size_t need = frame_ws_bytes(H, W, r);
   void* ws = nullptr;
   hipError_t e = hipMallocAsync(&ws, need, s);
   if (e != hipSuccess) return hip_fail(e);
@@ -355,7 +440,7 @@ size_t ipb_batch_plan_bytes(int n) {
 size_t ipb_batch_workspace_bytes(const ipb_frame* frames, int n, const ipb_params* p) {
   Resolved r;
   if (resolve(p, &r) != IPB_OK || check_frames(frames, n) != IPB_OK) return 0;
-  return batch_bytes(frames, n);
+  return batch_bytes(frames, n, r);
 }
 
 int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p, void* ws, size_t ws_bytes,
@@ -366,7 +451,7 @@ int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p, void* ws
   st = check_frames(frames, n);
   if (st != IPB_OK) return st;
   if (plan_host == nullptr || plan_bytes < ipb_batch_plan_bytes(n)) return IPB_ERR_INVALID_ARG;
-  if (ws == nullptr || ws_bytes < batch_bytes(frames, n) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+  if (ws == nullptr || ws_bytes < batch_bytes(frames, n, r) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
     return IPB_ERR_WORKSPACE;
   for (int i = 0; i < n; ++i) {
     const size_t nb = sizeof(float) * (size_t)frames[i].H * frames[i].W;
@@ -394,30 +479,11 @@ int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase, i
   if (st != IPB_OK) return st;
   if (plan_dev == nullptr || phase < -1 || phase > 2) return IPB_ERR_INVALID_ARG;
   if (max_tiles_local < 1 || max_tiles_global < 1 || max_cols < 1) return IPB_ERR_INVALID_ARG;
-  int dev = 0;
-  st = device_cus(&dev);
-  if (st != IPB_OK) return st;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   FrameSource src;
   std::memset(&src, 0, sizeof(src));
   src.plan = static_cast<const PlanHeader*>(plan_dev);
-  const int cus = g_dev[dev].cus;
-  hipError_t e;
-  if (phase == -1 || phase == 0) {
-    e = launch_reset(src, max_cols, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  if (phase == -1 || phase == 1) {
-    const int grid = std::min(max_tiles_local, resident(dev, 1, r.ltile, r.halo) * cus);
-    e = launch_local(src, r.kp, r.ltile, r.halo, grid, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  if (phase == -1 || phase == 2) {
-    const int grid = std::min(max_tiles_global, resident(dev, 2, r.gtile, 0) * cus);
-    e = launch_global(src, r.kp, r.gtile, grid, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  return IPB_OK;
+  return launch_phases(src, r, phase, 9, max_tiles_local, max_tiles_global, max_cols, true,
+                       static_cast<hipStream_t>(stream));
 }
 
 int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p, void* ws, size_t ws_bytes,
@@ -427,7 +493,7 @@ int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p, void
   if (st != IPB_OK) return st;
   st = check_frames(frames, n);
   if (st != IPB_OK) return st;
-  if (ws == nullptr || ws_bytes < batch_bytes(frames, n) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+  if (ws == nullptr || ws_bytes < batch_bytes(frames, n, r) || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
     return IPB_ERR_WORKSPACE;
   for (int i = 0; i < n; ++i) {
     const size_t nb = sizeof(float) * (size_t)frames[i].H * frames[i].W;
@@ -488,24 +554,21 @@ int ipb_last_hip_error(void) { return g_last_hip; }
 
 int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols) {
   if (rows == nullptr || cols == nullptr) return IPB_ERR_INVALID_ARG;
-  if (tile_id == 0) tile_id = 1;
-  if (phase == 1 && tile_id >= 1 && tile_id <= num_local_tiles()) {
-    *rows = local_tile_rows(tile_id);
-    *cols = local_tile_cols(tile_id);
+  if (tile_id == 0) tile_id = 5;
+  if (tile_id < 1 || tile_id > kTileIds) return IPB_ERR_INVALID_ARG;
+  if (phase == 1) {
+    *rows = tile_id >= 5 ? stream_local_tile_rows(tile_id) : local_tile_rows(tile_id);
+    *cols = tile_id >= 5 ? stream_local_tile_cols(tile_id) : local_tile_cols(tile_id);
     return IPB_OK;
   }
-  if (phase == 2 && tile_id >= 1 && tile_id <= num_global_tiles()) {
-    *rows = global_tile_rows(tile_id);
-    *cols = global_tile_cols(tile_id);
+  if (phase == 2) {
+    *rows = tile_id >= 5 ? stream_global_tile_rows(tile_id) : global_tile_rows(tile_id);
+    *cols = tile_id >= 5 ? stream_global_tile_cols(tile_id) : global_tile_cols(tile_id);
     return IPB_OK;
   }
   return IPB_ERR_INVALID_ARG;
 }
 
-int ipb_tile_count(int phase) {
-  if (phase == 1) return num_local_tiles();
-  if (phase == 2) return num_global_tiles();
-  return 0;
-}
+int ipb_tile_count(int phase) { return (phase == 1 || phase == 2) ? kTileIds : 0; }
 
 }  // extern "C"

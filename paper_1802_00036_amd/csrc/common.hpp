@@ -29,7 +29,8 @@ struct FrameDesc {
   int32_t gtile0;     // first phase-2 tile
   int32_t lcols;      // phase-1 tiles per row of tiles
   int32_t gcols;      // phase-2 tiles per row of tiles
-  int32_t pad0, pad1;
+  float* v6p;         // stage-6 values of the cells that were empty after stage 5 (H * W floats;
+                      // only those cells are written and read)
 };
 
 // Device-resident launch plan: header followed by n FrameDesc.
@@ -41,7 +42,9 @@ struct PlanHeader {
   int32_t* top_base;  // column tables of all frames, contiguous
   int32_t lt_rows, lt_cols;   // phase-1 tile shape the plan was built for
   int32_t gt_rows, gt_cols;   // phase-2 tile shape
-  int32_t pad[6];
+  int32_t* slow;              // phase-2 tile queues, see SlowQueue
+  int32_t slow_cap;           // capacity of each queue (phase-2 tiles of the launch)
+  int32_t pad[3];
 };
 static_assert(sizeof(PlanHeader) == 64, "plan header layout");
 static_assert(sizeof(FrameDesc) == 64, "frame descriptor layout");
@@ -70,10 +73,39 @@ struct FrameSource {
   FrameDesc single;
   int32_t single_ltiles;
   int32_t single_gtiles;
+  int32_t* slow;            // single frame: phase-2 tile queues, see SlowQueue
+  int32_t slow_cap;
 };
+
+// Queues of the streaming phase 2, in the workspace (cap = phase-2 tiles):
+//   slow[0]                 quarters (a tile id in the low 27 bits, the
+//                           quarter above) whose input rows still hold an
+//                           empty cell after the extension: they need the
+//                           31x31 fill (k_fill_pixels, then a second pass);
+//   slow[1]                 tiles of frames under 3 rows or columns,
+//                           recomputed by the LDS kernel;
+//   slow[2 .. 2+4cap)       the first queue, slow[2+4cap .. 2+5cap) the second.
+__host__ __device__ inline size_t slow_queue_ints(int cap) { return 2 + 5 * (size_t)cap; }
+__host__ __device__ inline int lds_queue_offset(int cap) { return 2 + 4 * cap; }
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_reset(const FrameSource& src, int max_cols, hipStream_t s);
+hipError_t launch_global_slow(const FrameSource& src, const KParams& kp, int stream_rows, int stream_cols,
+                              int grid, hipStream_t s);
+int slow_subtiles(int stream_rows, int stream_cols);
+int slow_resident_blocks();
+
+// Streaming kernels (stream.hip).
+int stream_local_tile_rows(int id);
+int stream_local_tile_cols(int id);
+int stream_global_tile_rows(int id);
+int stream_global_tile_cols(int id);
+bool stream_local_supported(int shape, int rd, int rc, int rf);
+bool stream_global_supported(int rm, int rg);
+hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s);
+hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s);
+hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s);
+int stream_resident_blocks(int phase, int tile_id, const KParams& kp);
 hipError_t launch_local(const FrameSource& src, const KParams& kp, int tile_id, int halo,
                         int grid, hipStream_t s);
 hipError_t launch_global(const FrameSource& src, const KParams& kp, int tile_id,

@@ -216,14 +216,17 @@ __device__ __forceinline__ void small_fill_dispatch(int r, const float* src, int
   else if (r == 1) small_fill<1>(src, pitch, r0, r1, c0, c1, oy, ox, H, W, thr, dst, top);
 }
 
-// Copy the in-image cells of the tile window of an LDS buffer to global.
+// Copy the in-image cells of the tile window of an LDS buffer to global
+// (rows below ylim and columns left of xlim only).
 __device__ void store_tile(const float* buf, int pitch, int bcol0, int r0, int r1, int c0, int c1,
-                           int oy, int ox, int H, int W, float* dst) {
+                           int oy, int ox, int H, int W, float* dst, int ylim = 0x7fffffff,
+                           int xlim = 0x7fffffff) {
   const int nc = c1 - c0, n = (r1 - r0) * nc;
   for (int i = threadIdx.x; i < n; i += kThreads) {
     const int r = r0 + i / nc, c = c0 + i % nc;
     const int gy = oy + r, gx = ox + c;
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W) dst[(size_t)gy * W + gx] = buf[r * pitch + (c - bcol0)];
+    if (gy >= 0 && gy < H && gy < ylim && gx >= 0 && gx < W && gx < xlim)
+      dst[(size_t)gy * W + gx] = buf[r * pitch + (c - bcol0)];
   }
 }
 
@@ -401,8 +404,9 @@ __device__ void reflect_fixup(float* B, int bpitch, int bcol0, int r0, int r1, i
 // masked by the median output, then the output inversion.
 template <int RG>
 __device__ void gauss_out(const float* B, int bpitch, int bcol0, int r0, int r1, int c0, int c1,
-                          int oy, int ox, int H, int W, const KParams& kp, float* dst, bool stage8) {
-  const int rb = min(r1, H - oy), cb = min(c1, W - ox);
+                          int oy, int ox, int H, int W, const KParams& kp, float* dst, bool stage8,
+                          int ylim, int xlim) {
+  const int rb = min(r1, min(ylim, H) - oy), cb = min(c1, min(xlim, W) - ox);
   const double w0 = kp.gw[0], w1 = kp.gw[1], w2 = kp.gw[2], sc = kp.gscale;
   const float thr = kp.thr, off = kp.off;
   for_column_runs(r0, rb, c0, cb, [&](int c, int ya, int yb) {
@@ -436,8 +440,9 @@ __device__ void gauss_out(const float* B, int bpitch, int bcol0, int r0, int r1,
 
 // Gaussian off: output inversion of the median map.
 __device__ void plain_out(const float* B, int bpitch, int bcol0, int r0, int r1, int c0, int c1,
-                          int oy, int ox, int H, int W, const KParams& kp, float* dst, bool stage8) {
-  const int rb = min(r1, H - oy), cb = min(c1, W - ox);
+                          int oy, int ox, int H, int W, const KParams& kp, float* dst, bool stage8,
+                          int ylim, int xlim) {
+  const int rb = min(r1, min(ylim, H) - oy), cb = min(c1, min(xlim, W) - ox);
   for_column_runs(r0, rb, c0, cb, [&](int c, int ya, int yb) {
     for (int y = ya; y < yb; ++y) {
       const float v7 = B[y * bpitch + (c - bcol0)];
@@ -453,7 +458,7 @@ constexpr int kHG = 19;   // phase-2 halo: 15 (31x31 fill) + 2 (median) + 2 (Gau
 // Phase 2: stages 5-9 of one TH x TW tile.
 template <int TH, int TW>
 __device__ void global_tile(const FrameDesc& f, const KParams& kp, int ty0, int tx0, float* A, float* B,
-                            int* s_top, float* s_topv) {
+                            int* s_top, float* s_topv, int ylim = 0x7fffffff, int xlim = 0x7fffffff) {
   constexpr int RH = TH + 2 * kHG, RW = TW + 2 * kHG, BW = TW + 8, B0 = kHG - 4;
   const int oy = ty0 - kHG, ox = tx0 - kHG;
   const int H = f.H, W = f.W;
@@ -496,7 +501,10 @@ __device__ void global_tile(const FrameDesc& f, const KParams& kp, int ty0, int 
     }
   }
   const bool any_empty = __syncthreads_or(empty) != 0;
-  if (kp.last_stage == 5) { store_tile(A, RW, 0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, f.out); return; }
+  if (kp.last_stage == 5) {
+    store_tile(A, RW, 0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, f.out, ylim, xlim);
+    return;
+  }
 
   // Stage 6: large hole fill, only where something is left to fill.
   if (kp.extrapolate && any_empty) {
@@ -512,7 +520,10 @@ __device__ void global_tile(const FrameDesc& f, const KParams& kp, int ty0, int 
     vfill_pass(rl, A, RW, B, BW, B0, n0, n1, m0, m1, thr);
     __syncthreads();
   }
-  if (kp.last_stage == 6) { store_tile(A, RW, 0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, f.out); return; }
+  if (kp.last_stage == 6) {
+    store_tile(A, RW, 0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, f.out, ylim, xlim);
+    return;
+  }
 
   // Stage 7: median blur over the tile plus the Gaussian's reach.
   const int q0 = kHG - kp.rg, q1r = kHG + TH + kp.rg, q1c = kHG + TW + kp.rg;
@@ -520,7 +531,10 @@ __device__ void global_tile(const FrameDesc& f, const KParams& kp, int ty0, int 
   else if (kp.rm == 1) median_pass<1>(A, RW, B, BW, B0, q0, q1r, q0, q1c, oy, ox, H, W);
   else copy_pass(A, RW, B, BW, B0, q0, q1r, q0, q1c, oy, ox, H, W);
   __syncthreads();
-  if (kp.last_stage == 7) { store_tile(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, f.out); return; }
+  if (kp.last_stage == 7) {
+    store_tile(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, f.out, ylim, xlim);
+    return;
+  }
   if (kp.rg > 0) {
     reflect_fixup(B, BW, B0, q0, q1r, q0, q1c, oy, ox, H, W, kp.rg);
     __syncthreads();
@@ -528,9 +542,9 @@ __device__ void global_tile(const FrameDesc& f, const KParams& kp, int ty0, int 
 
   // Stages 8 and 9.
   const bool st8 = kp.last_stage == 8;
-  if (kp.rg == 2) gauss_out<2>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8);
-  else if (kp.rg == 1) gauss_out<1>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8);
-  else plain_out(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8);
+  if (kp.rg == 2) gauss_out<2>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
+  else if (kp.rg == 1) gauss_out<1>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
+  else plain_out(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
 }
 
 template <int TH, int TW>
@@ -553,10 +567,43 @@ __global__ __launch_bounds__(kThreads) void k_global(FrameSource src, KParams kp
   }
 }
 
-// Column tables of every frame of a launch: reset to "no non-empty row".
+// Phase 2, queued tiles of frames under 3 rows or columns (whose reflect-101
+// border the streaming kernel does not handle): streaming tiles (srows x
+// scols) recomputed with the LDS tile code, each covered by TH x TW LDS tiles
+// clipped to the streaming tile.
+template <int TH, int TW>
+__global__ __launch_bounds__(kThreads) void k_global_slow(FrameSource src, KParams kp, int srows, int scols) {
+  constexpr int RH = TH + 2 * kHG, RW = TW + 2 * kHG, BW = TW + 8;
+  __shared__ float A[RH * RW];
+  __shared__ float B[RH * BW];
+  __shared__ int s_top[RW];
+  __shared__ float s_topv[RW];
+  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
+  const int count = slow[1];
+  const int32_t* queue = slow + lds_queue_offset(cap);
+  const int nsy = (srows + TH - 1) / TH, nsx = (scols + TW - 1) / TW, per = nsy * nsx;
+  for (int i = blockIdx.x; i < count * per; i += gridDim.x) {
+    const int t = queue[i / per], j = i % per;
+    FrameDesc f;
+    if (src.plan) f = plan_frames(src.plan)[find_frame<false>(src.plan, t)];
+    else f = src.single;
+    const int gt = t - f.gtile0;
+    const int tr = gt / f.gcols;
+    const int sy0 = tr * srows, sx0 = (gt - tr * f.gcols) * scols;
+    const int ty0 = sy0 + (j / nsx) * TH, tx0 = sx0 + (j % nsx) * TW;
+    if (ty0 < f.H && tx0 < f.W) global_tile<TH, TW>(f, kp, ty0, tx0, A, B, s_top, s_topv, sy0 + srows, sx0 + scols);
+    __syncthreads();
+  }
+}
+
+// Column tables of every frame of a launch: reset to "no non-empty row";
+// empty the queue of tiles that need the 31x31 fill.
 __global__ __launch_bounds__(kThreads) void k_reset(FrameSource src) {
   int32_t* base = src.plan ? src.plan->top_base : src.single.top;
   const int n = src.plan ? src.plan->ncols : src.single.W;
+  int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  if (blockIdx.x == 0 && threadIdx.x < 2 && slow != nullptr) slow[threadIdx.x] = 0;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) base[i] = kNoTop;
 }
 
@@ -618,6 +665,16 @@ hipError_t launch_global(const FrameSource& src, const KParams& kp, int tile_id,
 #undef X
   return hipErrorInvalidValue;
 }
+
+hipError_t launch_global_slow(const FrameSource& src, const KParams& kp, int stream_rows, int stream_cols,
+                              int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_global_slow<32, 64>), dim3(grid), dim3(kThreads), 0, s, src, kp, stream_rows, stream_cols);
+  return hipGetLastError();
+}
+
+int slow_subtiles(int stream_rows, int stream_cols) { return ((stream_rows + 31) / 32) * ((stream_cols + 63) / 64); }
+
+int slow_resident_blocks() { return occupancy(k_global_slow<32, 64>); }
 
 int max_resident_blocks(int phase, int tile_id, int halo) {
   if (phase == 1) {

@@ -1,0 +1,776 @@
+// Streaming gfx950 kernels for the default chain (Ku, Harakeh & Waslander
+// 2018, Sec. III): one wave64 per tile, two neighbouring columns per lane,
+// rows streamed top to bottom through register ring buffers.  Neighbouring
+// columns come from the adjacent lanes by DPP row moves (wave_shr/wave_shl),
+// so the fast path uses no LDS and no barriers.
+//
+//   k_local_stream  : stages 1-4 (inversion, kernel dilation, 5x5 closing,
+//                     7x7 small fill); 128 input columns -> 108 output columns.
+//   k_global_stream : stages 5, 7, 8, 9 (extension on load, 5x5 median,
+//                     Gaussian, output inversion); 128 input columns -> 120
+//                     output columns.  A tile whose needed cells still hold an
+//                     empty pixel after the extension needs the 31x31 fill
+//                     (stage 6): its quarters are queued; k_fill_pixels
+//                     computes the fill at the empty cells and
+//                     k_global_patched runs those quarters again.
+//
+// Border rules are the ones of the LDS kernels: morphology ignores cells
+// outside the image, the median replicates the border, the Gaussian reflects
+// about the edge pixel (reflect-101).
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "networks.hpp"
+
+#pragma clang fp contract(off)
+
+namespace ipb {
+namespace {
+
+constexpr int kLanes = 64;
+constexpr int kInfKey = 0x7f800000;   // +inf
+
+// Selection works on ordering keys: the bit patterns of the map values read
+// as int32.  Every map value is +0, a positive finite float or +inf, and for
+// those the integer order of the bit patterns is the float order, so integer
+// min/max select exactly the values float min/max would (and need no NaN
+// canonicalisation).
+__device__ __forceinline__ int key(float v) { return __float_as_int(v); }
+
+// Frame buffers are device (global) memory; say so, so that accesses use
+// global loads/stores with a scalar row base and a 32-bit lane offset.
+typedef __attribute__((address_space(1))) int gint;
+typedef __attribute__((address_space(1))) const int gcint;
+typedef __attribute__((address_space(1))) const float gcfloat;
+__device__ __forceinline__ gcint* gc(const void* p) { return (gcint*)(const int*)p; }
+__device__ __forceinline__ gcfloat* gcf(const float* p) { return (gcfloat*)p; }
+__device__ __forceinline__ gint* gw(void* p) { return (gint*)(int*)p; }
+typedef __attribute__((address_space(1))) const char gcchar;
+typedef __attribute__((address_space(1))) char gchar;
+// element at a 32-bit byte offset from a (uniform) row base
+__device__ __forceinline__ int ldk(gcint* row, unsigned off) { return *(gcint*)((gcchar*)row + off); }
+__device__ __forceinline__ float ldf(gcfloat* row, unsigned off) { return *(gcfloat*)((gcchar*)row + off); }
+__device__ __forceinline__ void stk(gint* row, unsigned off, int v) { *(gint*)((gchar*)row + off) = v; }
+__device__ __forceinline__ float val(int k) { return __int_as_float(k); }
+
+// lane i receives lane i-1's value (lane 0 receives 0; its neighbours are
+// outside the tile's input columns and never feed an output)
+__device__ __forceinline__ int from_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+// lane i receives lane i+1's value (lane 63 receives 0)
+__device__ __forceinline__ int from_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+__device__ __forceinline__ int min3i(int a, int b, int c) { return min(min(a, b), c); }
+__device__ __forceinline__ int clampi_s(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ int xcd_tile_s(int b, int g) {
+  if ((g & 7) != 0) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+// The frame of a tile is the same for the whole wave: keep it in scalar
+// registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <class P>
+__device__ __forceinline__ P* uni_ptr(P* p) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+  return reinterpret_cast<P*>(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ FrameDesc uniform_frame(const FrameDesc& f) {
+  FrameDesc u;
+  u.in = uni_ptr(f.in);
+  u.out = uni_ptr(f.out);
+  u.v4 = uni_ptr(f.v4);
+  u.top = uni_ptr(f.top);
+  u.H = uni(f.H);
+  u.W = uni(f.W);
+  u.ltile0 = uni(f.ltile0);
+  u.gtile0 = uni(f.gtile0);
+  u.lcols = uni(f.lcols);
+  u.gcols = uni(f.gcols);
+  u.v6p = uni_ptr(f.v6p);
+  return u;
+}
+
+template <bool LOCAL>
+__device__ __forceinline__ int find_frame_s(const PlanHeader* p, int t) {
+  const FrameDesc* f = reinterpret_cast<const FrameDesc*>(p + 1);
+  int lo = 0, hi = p->n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int start = LOCAL ? f[mid].ltile0 : f[mid].gtile0;
+    if (start <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Stage-2 kernel rows: row dy of the kernel is the centred interval
+// |dx| <= se_half(dy) (full, cross, diamond, circle).
+template <int SHAPE, int R>
+__host__ __device__ constexpr int se_half_s(int dy) {
+  const int ady = dy < 0 ? -dy : dy;
+  if (SHAPE == 0) return R;
+  if (SHAPE == 1) return ady == 0 ? R : 0;
+  if (SHAPE == 2) return R - ady;
+  int e = 0;
+  while (e < R && 4 * ((e + 1) * (e + 1) + ady * ady) <= (2 * R + 1) * (2 * R + 1)) ++e;
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// Phase 1, streaming: stages 1-4 for 108 x TH output cells per wave.
+constexpr int kLocalHalo = 10;                         // >= RD + 2 + 2 + 3 for RD <= 3
+constexpr int kLocalTW = 2 * kLanes - 2 * kLocalHalo;  // 108
+
+template <int SHAPE, int RD, int TH>
+__device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0, int tx0, int lane) {
+  const int H = f.H, W = f.W;
+  const float thr = kp.thr, off = kp.off;
+  const int kthr = key(thr);
+  const int ca = tx0 - kLocalHalo + 2 * lane, cb = ca + 1;
+  const bool ina = ca >= 0 && ca < W, inb = cb >= 0 && cb < W;
+  const bool lane_out = lane >= kLocalHalo / 2 && lane < kLocalHalo / 2 + kLocalTW / 2;
+  const bool outa = lane_out && ina, outb = lane_out && inb;
+  const unsigned ua = 4u * (unsigned)ca, ub = ua + 4u;   // byte offsets, used only when in the image
+  const int last = kp.last_stage;
+  constexpr int D2 = RD, D3A = RD + 2, D3B = RD + 4, D4 = RD + 7;  // row delays of the stage outputs
+  const int q0 = ty0 - D4;
+  const int n = TH + 2 * D4;
+
+  // ring buffers (slot = relative row & 7), ordering keys
+  int h[8][RD + 1][2];        // stage-2 horizontal maxima per radius
+  int hd[8][2];               // stage-3a horizontal max
+  int he[8][2];               // stage-3b horizontal min
+  int hf[8][2];               // stage-4 horizontal max
+  int v3[8][2];               // stage-3 map (centre of the fill)
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+#pragma unroll
+    for (int e = 0; e <= RD; ++e) h[s][e][0] = h[s][e][1] = 0;
+    hd[s][0] = hd[s][1] = 0;
+    he[s][0] = he[s][1] = kInfKey;
+    hf[s][0] = hf[s][1] = 0;
+    v3[s][0] = v3[s][1] = 0;
+  }
+  int first_a = kNoTop, first_b = kNoTop;
+  gint* dst = gw(last >= 5 ? f.v4 : f.out);
+  gcfloat* in = gcf(f.in);
+
+  // input rows are fetched 8 rows ahead of their use
+  float da[8], db[8];
+  auto fetch = [&](int r, float& xa_, float& xb_) {
+    const int q = q0 + r;
+    xa_ = 0.f;
+    xb_ = 0.f;
+    if (r < n && q >= 0 && q < H) {
+      gcfloat* row = in + (size_t)q * W;
+      if (ina) xa_ = ldf(row, ua);
+      if (inb) xb_ = ldf(row, ub);
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < 8; ++u) fetch(u, da[u], db[u]);
+
+  for (int rb = 0; rb < n; rb += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = rb + u;
+      if (r >= n) break;
+      const int q = q0 + r;
+
+      // Stage 1: inversion of input row q.
+      int va, vb;
+      {
+        const float d0 = da[u], d1 = db[u];
+        fetch(r + 8, da[u], db[u]);
+        const float v0 = off - d0, v1 = off - d1;
+        va = (d0 > thr && v0 > thr) ? key(v0) : 0;
+        vb = (d1 > thr && v1 > thr) ? key(v1) : 0;
+      }
+      if (last == 1 && q >= ty0 && q < ty0 + TH && q < H) {
+        gint* o = dst + (size_t)q * W;
+        if (outa) stk(o, ua, va);
+        if (outb) stk(o, ub, vb);
+      }
+
+      // Stage 2: kernel dilation; horizontal maxima of row q, then the
+      // vertical combination for row q - RD.
+      {
+        const int La = from_prev(va), Lb = from_prev(vb), Ra = from_next(va), Rb = from_next(vb);
+        h[u][0][0] = va;
+        h[u][0][1] = vb;
+        if constexpr (RD >= 1) { h[u][1][0] = max3i(Lb, va, vb); h[u][1][1] = max3i(va, vb, Ra); }
+        if constexpr (RD >= 2) { h[u][2][0] = max3i(h[u][1][0], La, Ra); h[u][2][1] = max3i(h[u][1][1], Lb, Rb); }
+        if constexpr (RD >= 3) {
+          const int LLb = from_prev(Lb), RRa = from_next(Ra);
+          h[u][3][0] = max3i(h[u][2][0], LLb, Rb);
+          h[u][3][1] = max3i(h[u][2][1], La, RRa);
+        }
+      }
+      const int p2 = q - D2;
+      int w2a = h[(u - RD) & 7][se_half_s<SHAPE, RD>(0)][0];
+      int w2b = h[(u - RD) & 7][se_half_s<SHAPE, RD>(0)][1];
+#pragma unroll
+      for (int dy = -RD; dy <= RD; ++dy) {
+        if (dy == 0) continue;
+        w2a = max(w2a, h[(u - RD + dy) & 7][se_half_s<SHAPE, RD>(dy)][0]);
+        w2b = max(w2b, h[(u - RD + dy) & 7][se_half_s<SHAPE, RD>(dy)][1]);
+      }
+      const bool row2 = p2 >= 0 && p2 < H;
+      w2a = (row2 && ina) ? w2a : 0;
+      w2b = (row2 && inb) ? w2b : 0;
+      if (last == 2 && p2 >= ty0 && p2 < ty0 + TH && p2 < H) {
+        gint* o = dst + (size_t)p2 * W;
+        if (outa) stk(o, ua, w2a);
+        if (outb) stk(o, ub, w2b);
+      }
+
+      // Stage 3a: 5x5 dilation; horizontal max of stage-2 row p2.
+      {
+        const int La = from_prev(w2a), Lb = from_prev(w2b), Ra = from_next(w2a), Rb = from_next(w2b);
+        const int t = max3i(Lb, w2a, w2b);
+        hd[u][0] = max3i(t, La, Ra);
+        hd[u][1] = max3i(t, Ra, Rb);
+      }
+      const int p3 = q - D3A;
+      int ta = max3i(max3i(hd[(u - 4) & 7][0], hd[(u - 3) & 7][0], hd[(u - 2) & 7][0]), hd[(u - 1) & 7][0], hd[u][0]);
+      int tb = max3i(max3i(hd[(u - 4) & 7][1], hd[(u - 3) & 7][1], hd[(u - 2) & 7][1]), hd[(u - 1) & 7][1], hd[u][1]);
+      const bool row3 = p3 >= 0 && p3 < H;
+      ta = (row3 && ina) ? ta : kInfKey;
+      tb = (row3 && inb) ? tb : kInfKey;
+
+      // Stage 3b: 5x5 erosion; horizontal min of row p3.
+      {
+        const int La = from_prev(ta), Lb = from_prev(tb), Ra = from_next(ta), Rb = from_next(tb);
+        const int t = min3i(Lb, ta, tb);
+        he[u][0] = min3i(t, La, Ra);
+        he[u][1] = min3i(t, Ra, Rb);
+      }
+      const int p4 = q - D3B;
+      int ea = min3i(min3i(he[(u - 4) & 7][0], he[(u - 3) & 7][0], he[(u - 2) & 7][0]), he[(u - 1) & 7][0], he[u][0]);
+      int eb = min3i(min3i(he[(u - 4) & 7][1], he[(u - 3) & 7][1], he[(u - 2) & 7][1]), he[(u - 1) & 7][1], he[u][1]);
+      const bool row4 = p4 >= 0 && p4 < H;
+      ea = (row4 && ina) ? ea : 0;
+      eb = (row4 && inb) ? eb : 0;
+      v3[u][0] = ea;
+      v3[u][1] = eb;
+      if (last == 3 && p4 >= ty0 && p4 < ty0 + TH && p4 < H) {
+        gint* o = dst + (size_t)p4 * W;
+        if (outa) stk(o, ua, ea);
+        if (outb) stk(o, ub, eb);
+      }
+
+      // Stage 4: 7x7 fill of empty pixels; horizontal max of row p4, then
+      // the vertical max and the select for row p4 - 3.
+      {
+        const int La = from_prev(ea), Lb = from_prev(eb), Ra = from_next(ea), Rb = from_next(eb);
+        const int LLb = from_prev(Lb), RRa = from_next(Ra);
+        const int t = max(max3i(max3i(La, Lb, ea), eb, Ra), Rb);
+        hf[u][0] = max(t, LLb);
+        hf[u][1] = max(t, RRa);
+      }
+      const int o4 = q - D4;
+      if (last >= 4 && o4 >= ty0 && o4 < ty0 + TH && o4 < H) {
+        const int ma = max3i(max3i(hf[(u - 6) & 7][0], hf[(u - 5) & 7][0], hf[(u - 4) & 7][0]),
+                             max3i(hf[(u - 3) & 7][0], hf[(u - 2) & 7][0], hf[(u - 1) & 7][0]), hf[u][0]);
+        const int mb = max3i(max3i(hf[(u - 6) & 7][1], hf[(u - 5) & 7][1], hf[(u - 4) & 7][1]),
+                             max3i(hf[(u - 3) & 7][1], hf[(u - 2) & 7][1], hf[(u - 1) & 7][1]), hf[u][1]);
+        const int c3a = v3[(u - 3) & 7][0], c3b = v3[(u - 3) & 7][1];
+        const int oa = c3a <= kthr ? ma : c3a;
+        const int ob = c3b <= kthr ? mb : c3b;
+        gint* o = dst + (size_t)o4 * W;
+        if (outa) {
+          stk(o, ua, oa);
+          if (oa > kthr && first_a == kNoTop) first_a = o4;
+        }
+        if (outb) {
+          stk(o, ub, ob);
+          if (ob > kthr && first_b == kNoTop) first_b = o4;
+        }
+      }
+    }
+  }
+  if (last >= 5) {
+    if (outa && first_a != kNoTop) atomicMin(f.top + ca, first_a);
+    if (outb && first_b != kNoTop) atomicMin(f.top + cb, first_b);
+  }
+}
+
+template <int SHAPE, int RD, int TH>
+__global__ __launch_bounds__(kLanes) void k_local_stream(FrameSource src, KParams kp) {
+  const int lane = threadIdx.x;
+  const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
+  for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+    FrameDesc f;
+    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[find_frame_s<true>(src.plan, t)];
+    else f = src.single;
+    f = uniform_frame(f);
+    const int lt = t - f.ltile0;
+    const int tr = lt / f.lcols;
+    local_stream_tile<SHAPE, RD, TH>(f, kp, tr * TH, (lt - tr * f.lcols) * kLocalTW, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase 2, streaming.
+
+constexpr int kGlobalTW = 2 * kLanes - 8;   // 120
+
+// Remove one occurrence of `out` from the sorted 5-window s and insert `in`
+// (ordering keys).
+__device__ __forceinline__ void window_update(int* s, int out, int in) {
+  const int t0 = s[0] < out ? s[0] : s[1];
+  const int t1 = s[1] < out ? s[1] : s[2];
+  const int t2 = s[2] < out ? s[2] : s[3];
+  const int t3 = s[3] < out ? s[3] : s[4];
+  s[0] = min(t0, in);
+  // clamp(in, t_{i-1}, t_i) as one v_med3 on the keys' float values (all
+  // non-negative, no NaN: the same order as the keys)
+  s[1] = key(__builtin_amdgcn_fmed3f(val(in), val(t0), val(t1)));
+  s[2] = key(__builtin_amdgcn_fmed3f(val(in), val(t1), val(t2)));
+  s[3] = key(__builtin_amdgcn_fmed3f(val(in), val(t2), val(t3)));
+  s[4] = max(t3, in);
+}
+
+__device__ __forceinline__ double hsum5(double wc, double w1, double w2, int m2, int m1, int c, int p1, int p2) {
+  // exact for the binomial taps (integer weights): every partial sum fits
+  // in the 53-bit significand
+  const double s2 = (double)val(m2) + (double)val(p2);
+  const double s1 = (double)val(m1) + (double)val(p1);
+  return fma(wc, (double)val(c), fma(w1, s1, w2 * s2));
+}
+
+// Stages 5-9 of one streaming tile (TH x 120 output cells).  First pass
+// (PATCHED false): the stage-6 map is taken to equal the stage-5 map; tiles
+// where that does not hold are queued by quarter.  Second pass (PATCHED
+// true, one quarter): cells empty after stage 5 read their stage-6 value
+// from f.v6p (written by k_fill_pixels).
+template <int TH, bool PATCHED>
+__device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int ty0, int tx0, int lane,
+                                   int32_t* slow, int cap) {
+  const int H = f.H, W = f.W;
+  const float thr = kp.thr, off = kp.off;
+  const int kthr = key(thr);
+  const int last = kp.last_stage;
+  const bool median = kp.rm == 2;
+  if (!PATCHED && (H < 3 || W < 3)) {   // reflect-101 on tiny frames: leave it to the LDS kernel
+    if (lane == 0) slow[lds_queue_offset(cap) + atomicAdd(slow + 1, 1)] = t;
+    return;
+  }
+  const int ca = tx0 - 4 + 2 * lane, cb = ca + 1;
+  const int xa = clampi_s(ca, 0, W - 1), xb = clampi_s(cb, 0, W - 1);     // replicated border columns
+  const unsigned oxa = 4u * (unsigned)xa, oxb = 4u * (unsigned)xb;
+  const bool ina = ca >= 0 && ca < W, inb = cb >= 0 && cb < W;
+  const bool lane_out = lane >= 2 && lane < 62;
+  const bool outa = lane_out && ina, outb = lane_out && inb;
+  const unsigned ua = 4u * (unsigned)ca, ub = ua + 4u;   // byte offsets, used only when in the image
+  const bool edge_cols = tx0 - 4 < 0 || tx0 + kGlobalTW + 4 > W;
+  gcint* v4 = gc(f.v4);
+  gint* out = gw(f.out);
+
+  // Stage 5 (extension to top of frame): the row and value each column copies up.
+  int topa = 0, topb = 0, tva = 0, tvb = 0;
+  if (kp.extrapolate) {
+    gcint* top = gc(f.top);
+    const int t_a = top[xa], t_b = top[xb];
+    if (t_a < H) { topa = t_a; tva = v4[(size_t)t_a * W + xa]; }
+    if (t_b < H) { topb = t_b; tvb = v4[(size_t)t_b * W + xb]; }
+  }
+
+  // reflect-101 source lane/slot of this lane's columns, for the Gaussian's border
+  int sla = 0, slb = 0;
+  bool sela = false, selb = false;
+  if (edge_cols) {
+    auto refl = [&](int c) {
+      if (c < 0) c = -c;
+      if (c >= W) c = 2 * W - 2 - c;
+      return c;
+    };
+    const int sa = refl(ca) - (tx0 - 4), sb = refl(cb) - (tx0 - 4);
+    sla = clampi_s(sa >> 1, 0, kLanes - 1);
+    slb = clampi_s(sb >> 1, 0, kLanes - 1);
+    sela = (sa & 1) != 0;
+    selb = (sb & 1) != 0;
+  }
+
+  const double wc = kp.gw[0], w1 = kp.gw[1], w2 = kp.gw[2], gsc = kp.gscale;
+  const int q0 = ty0 - 4;
+  const int n = TH + 8;
+  int raw[8][2];         // stage-5 keys (window of the median)
+  int s7[8][2];          // median output keys
+  double hs[8][2];       // Gaussian horizontal sums of the median rows
+  int Sa[5], Sb[5];      // sorted 5-row windows of the lane's two columns
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    raw[s][0] = raw[s][1] = kInfKey;
+    s7[s][0] = s7[s][1] = 0;
+    hs[s][0] = hs[s][1] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) Sa[k] = Sb[k] = kInfKey;
+  // quarters (TH/4 output rows each) whose input rows (+-4) hold an empty cell
+  unsigned qmask = 0;
+
+  // Stage 5 on load: rows of the stage-4 map (border rows replicated), the
+  // extension applied; fetched 8 rows ahead of their use.
+  int pa[8], pb[8];
+  gcint* v6p = gc(f.v6p);
+  auto fetch = [&](int r, int& xa_, int& xb_) {
+    const int gy = clampi_s(q0 + r, 0, H - 1);
+    xa_ = tva;
+    xb_ = tvb;
+    if (r < n) {
+      gcint* row = v4 + (size_t)gy * W;
+      if (gy >= topa) xa_ = ldk(row, oxa);
+      if (gy >= topb) xb_ = ldk(row, oxb);
+      if (PATCHED) {
+        gcint* prow = v6p + (size_t)gy * W;
+        if (xa_ <= kthr) xa_ = ldk(prow, oxa);
+        if (xb_ <= kthr) xb_ = ldk(prow, oxb);
+      }
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < 8; ++u) fetch(u, pa[u], pb[u]);
+
+  for (int rb = 0; rb < n; rb += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = rb + u;
+      if (r >= n) break;
+      const int q = q0 + r;
+      const int va = pa[u], vb = pb[u];
+      fetch(r + 8, pa[u], pb[u]);
+      if (q >= 0 && q < H) {
+        if (!PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
+          // row q is an input row of quarter k when 16k - 4 <= q - ty0 < 16k + 20 (TH/4 = 16)
+          const int rel = q - ty0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (rel >= k * (TH / 4) - 4 && rel < (k + 1) * (TH / 4) + 4) qmask |= 1u << k;
+        }
+        if ((last == 5 || last == 6) && q >= ty0 && q < ty0 + TH) {
+          gint* o = out + (size_t)q * W;
+          if (outa) stk(o, ua, va);
+          if (outb) stk(o, ub, vb);
+        }
+      }
+      if (median) {
+        window_update(Sa, raw[(u - 5) & 7][0], va);
+        window_update(Sb, raw[(u - 5) & 7][1], vb);
+      }
+      raw[u][0] = va;
+      raw[u][1] = vb;
+      if (r < 4) continue;
+
+      // Stage 7: median of row m = q - 2.
+      const int m = q - 2;
+      int v7a, v7b;
+      if (median) {
+        int Lb[5], La[5], Rb[5], m1[10], m2[10], core[6];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          Lb[k] = from_prev(Sb[k]);   // column a - 1
+          La[k] = from_prev(Sa[k]);   // column a - 2
+          Rb[k] = from_next(Sb[k]);   // column b + 2
+        }
+        net::merge5_5(Lb, Sa, m1);    // columns a - 1, a
+#pragma unroll
+        for (int k = 0; k < 10; ++k) m2[k] = from_next(m1[k]);   // columns b, b + 1
+        net::ranks7_12_of_10_10(m1, m2, core);
+        net::rank5_of_6_5(core, La, &v7a);
+        net::rank5_of_6_5(core, Rb, &v7b);
+      } else {
+        v7a = raw[(u - 2) & 7][0];
+        v7b = raw[(u - 2) & 7][1];
+      }
+      if (edge_cols) {   // out-of-image columns take the median of their reflect-101 column
+        const int fa0 = __shfl(v7a, sla), fa1 = __shfl(v7b, sla);
+        const int fb0 = __shfl(v7a, slb), fb1 = __shfl(v7b, slb);
+        if (!ina) v7a = sela ? fa1 : fa0;
+        if (!inb) v7b = selb ? fb1 : fb0;
+      }
+      s7[u][0] = v7a;
+      s7[u][1] = v7b;
+      if (last == 7 && m >= ty0 && m < ty0 + TH && m < H && m >= 0) {
+        gint* o = out + (size_t)m * W;
+        if (outa) stk(o, ua, v7a);
+        if (outb) stk(o, ub, v7b);
+      }
+
+      // Stage 8: horizontal sums of row m (reflect-101 rows are copies).
+      if (m >= 0) {
+        if (m < H) {
+          const int La = from_prev(v7a), Lb = from_prev(v7b), Ra = from_next(v7a), Rb = from_next(v7b);
+          hs[u][0] = hsum5(wc, w1, w2, La, Lb, v7a, v7b, Ra);
+          hs[u][1] = hsum5(wc, w1, w2, Lb, v7a, v7b, Ra, Rb);
+          if (m == 2 && q0 + 2 <= 0) {            // rows -1, -2 mirror rows 1, 2
+            hs[(u - 3) & 7][0] = hs[(u - 1) & 7][0];
+            hs[(u - 3) & 7][1] = hs[(u - 1) & 7][1];
+            hs[(u - 4) & 7][0] = hs[u][0];
+            hs[(u - 4) & 7][1] = hs[u][1];
+          }
+        } else if (m == H) {                      // row H mirrors H - 2
+          hs[u][0] = hs[(u - 2) & 7][0];
+          hs[u][1] = hs[(u - 2) & 7][1];
+        } else if (m == H + 1) {                  // row H + 1 mirrors H - 3
+          hs[u][0] = hs[(u - 4) & 7][0];
+          hs[u][1] = hs[(u - 4) & 7][1];
+        }
+      }
+      if (r < 8) continue;
+
+      // Stages 8 and 9 for row g = q - 4.
+      const int g = q - 4;
+      if (g >= ty0 && g < ty0 + TH && g < H && last >= 8) {
+        const int ca7 = s7[(u - 2) & 7][0], cb7 = s7[(u - 2) & 7][1];
+        const bool ma = ca7 > kthr, mb = cb7 > kthr;
+        float oa, ob;
+        if (kp.rg > 0) {
+          const double ga = fma(wc, hs[(u - 2) & 7][0],
+                                fma(w1, hs[(u - 3) & 7][0] + hs[(u - 1) & 7][0],
+                                    w2 * (hs[(u - 4) & 7][0] + hs[u][0])));
+          const double gb = fma(wc, hs[(u - 2) & 7][1],
+                                fma(w1, hs[(u - 3) & 7][1] + hs[(u - 1) & 7][1],
+                                    w2 * (hs[(u - 4) & 7][1] + hs[u][1])));
+          oa = ma ? (float)(ga * gsc) : 0.f;
+          ob = mb ? (float)(gb * gsc) : 0.f;
+        } else {
+          oa = ma ? val(ca7) : 0.f;
+          ob = mb ? val(cb7) : 0.f;
+        }
+        if (last == 9) {
+          oa = ma ? off - oa : 0.f;
+          ob = mb ? off - ob : 0.f;
+        }
+        gint* o = out + (size_t)g * W;
+        if (outa) stk(o, ua, key(oa));
+        if (outb) stk(o, ub, key(ob));
+      }
+    }
+  }
+  // Cells the median and blur need still hold an empty pixel: this tile
+  // needs the 31x31 fill; queue it for the LDS kernel.
+  // Those quarters need the 31x31 fill: queue them (tile id in the low 27
+  // bits, quarter above).
+  if (!PATCHED && kp.extrapolate && qmask != 0 && lane == 0) {
+    const int base = atomicAdd(slow, __popc(qmask));
+    int k = 0;
+    for (int qk = 0; qk < 4; ++qk)
+      if ((qmask >> qk) & 1u) slow[2 + base + k++] = t | (qk << 27);
+  }
+}
+
+template <int TH>
+__global__ __launch_bounds__(kLanes) void k_global_stream(FrameSource src, KParams kp) {
+  const int lane = threadIdx.x;
+  const int total = src.plan ? src.plan->gtiles : src.single_gtiles;
+  int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
+  for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+    FrameDesc f;
+    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[find_frame_s<false>(src.plan, t)];
+    else f = src.single;
+    f = uniform_frame(f);
+    const int gt = t - f.gtile0;
+    const int tr = gt / f.gcols;
+    global_stream_tile<TH, false>(f, kp, t, tr * TH, (gt - tr * f.gcols) * kGlobalTW, lane, slow, cap);
+  }
+}
+
+// Phase 2, queued quarters, step 1 (Sec. III "Large Hole Fill"): every cell
+// of the quarter's output rows that is empty after stage 5 takes the largest
+// stage-5 value of the full (2 rl + 1)^2 window around it (cells outside the
+// image ignored).  One wave per quarter; for each empty cell the wave's lanes
+// split the window (two lanes per window row, up to 16 columns each) and
+// reduce.  The values go to f.v6p at the cell; nothing else is written, so
+// the stage-5 reads of other waves are unaffected.
+constexpr int kFillRad = 15;   // largest large-fill radius (31x31)
+
+template <int TH>
+__global__ __launch_bounds__(kLanes) void k_fill_pixels(FrameSource src, KParams kp) {
+  constexpr int QR = TH / 4;
+  __shared__ int s_top[kGlobalTW + 2 * kFillRad];   // column tops of the window columns
+  const int lane = threadIdx.x;
+  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int count = slow[0];
+  const int rl = kp.rl;
+  const int kthr = key(kp.thr);
+  // window share of this lane: row y + dy, columns x + c_lo .. x + c_hi
+  const int dy = (lane >> 1) - rl;
+  const bool lrow = (lane >> 1) < 2 * rl + 1;
+  const int c_lo = -rl + 16 * (lane & 1), c_hi = min(rl, c_lo + 15);
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const int entry = slow[2 + i];
+    const int t = entry & ((1 << 27) - 1), qk = (unsigned)entry >> 27;
+    FrameDesc f;
+    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[find_frame_s<false>(src.plan, t)];
+    else f = src.single;
+    f = uniform_frame(f);
+    const int H = f.H, W = f.W;
+    const int gt = t - f.gtile0;
+    const int tr = gt / f.gcols;
+    const int y0 = tr * TH + qk * QR, tx0 = (gt - tr * f.gcols) * kGlobalTW;
+    gcint* v4 = gc(f.v4);
+    gcint* top = gc(f.top);
+    gint* v6p = gw(f.v6p);
+    __syncthreads();                                   // s_top of the previous quarter is no longer read
+    for (int c = lane; c < kGlobalTW + 2 * rl; c += kLanes) {
+      const int gx = tx0 - rl + c;
+      s_top[c] = (gx >= 0 && gx < W) ? top[gx] : H;    // >= H: no extension
+    }
+    __syncthreads();
+    // stage-5 value at (gy, gx), both clamped into the image and to the
+    // window columns: rows above the column's top take the top value.  The
+    // loads are unconditional (the callers mask the values), so that a
+    // batch of them is in flight at once.
+    const int wmax = kGlobalTW + 2 * rl - 1;
+    auto v5 = [&](int gy, int gx) -> int {
+      const int idx = clampi_s(gx - (tx0 - rl), 0, wmax);
+      const int x = clampi_s(tx0 - rl + idx, 0, W - 1);
+      const int y = clampi_s(gy, 0, H - 1);
+      const int tt = s_top[idx];
+      return v4[(size_t)(tt < H ? max(y, tt) : y) * W + x];
+    };
+    const int ca = tx0 + 2 * lane, cb = ca + 1;        // lanes 0..59 hold the 120 output columns
+    const bool ina = lane < 60 && ca < W, inb = lane < 60 && cb < W;
+    int va[QR], vb[QR];
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+      va[r] = v5(y0 + r, ca);
+      vb[r] = v5(y0 + r, cb);
+    }
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+      const bool rin = y0 + r < H;
+      va[r] = (ina && rin) ? va[r] : kInfKey;
+      vb[r] = (inb && rin) ? vb[r] : kInfKey;
+    }
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+      const int y = y0 + r;
+      unsigned long long ma = __ballot(va[r] <= kthr), mb = __ballot(vb[r] <= kthr);
+      while ((ma | mb) != 0) {
+        int x;
+        if (ma != 0) { const int l = __ffsll((long long)ma) - 1; ma &= ma - 1; x = tx0 + 2 * l; }
+        else { const int l = __ffsll((long long)mb) - 1; mb &= mb - 1; x = tx0 + 2 * l + 1; }
+        const int gy = y + dy;
+        const bool rok = lrow && gy >= 0 && gy < H;
+        int w[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) w[c] = v5(gy, x + c_lo + c);
+        int m = 0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int gx = x + c_lo + c;
+          m = max(m, (rok && c_lo + c <= c_hi && gx >= 0 && gx < W) ? w[c] : 0);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+        if (lane == 0) v6p[(size_t)y * W + x] = m;
+      }
+    }
+  }
+}
+
+// Phase 2, queued quarters, step 2: median, blur and output inversion of
+// the quarter again, with the stage-6 values of step 1.
+template <int TH>
+__global__ __launch_bounds__(kLanes) void k_global_patched(FrameSource src, KParams kp) {
+  constexpr int QR = TH / 4;
+  const int lane = threadIdx.x;
+  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int count = slow[0];
+  if (kp.last_stage == 5) return;                   // the stage-5 map needs no second pass
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const int entry = slow[2 + i];
+    const int t = entry & ((1 << 27) - 1), qk = (unsigned)entry >> 27;
+    FrameDesc f;
+    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[find_frame_s<false>(src.plan, t)];
+    else f = src.single;
+    f = uniform_frame(f);
+    const int gt = t - f.gtile0;
+    const int tr = gt / f.gcols;
+    global_stream_tile<QR, true>(f, kp, t, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane, nullptr, 0);
+  }
+}
+
+constexpr int stream_local_rows(int id) { return id == 5 ? 64 : id == 6 ? 128 : id == 7 ? 32 : 0; }
+constexpr int stream_global_rows(int id) { return id == 5 ? 64 : id == 6 ? 32 : id == 7 ? 128 : 0; }
+
+template <class K>
+int occupancy_s(K kernel) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kLanes, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace
+
+int stream_local_tile_rows(int id) { return stream_local_rows(id); }
+int stream_local_tile_cols(int id) { return stream_local_rows(id) ? kLocalTW : 0; }
+int stream_global_tile_rows(int id) { return stream_global_rows(id); }
+int stream_global_tile_cols(int id) { return stream_global_rows(id) ? kGlobalTW : 0; }
+
+bool stream_local_supported(int shape, int rd, int rc, int rf) {
+  if (rc != 2 || rf != 3) return false;
+  if (rd == 2) return true;                      // all four shapes, 5x5
+  return shape == 0 && (rd == 1 || rd == 3);      // full 3x3 and 7x7
+}
+
+bool stream_global_supported(int rm, int rg) { return (rm == 0 || rm == 2) && rg >= 0 && rg <= 2; }
+
+#define IPB_STREAM_LOCAL(X)                                                          \
+  X(2, 2, 5) X(1, 2, 5) X(0, 2, 5) X(3, 2, 5) X(0, 1, 5) X(0, 3, 5) X(2, 2, 6) X(2, 2, 7) \
+  X(1, 2, 6) X(0, 2, 6) X(3, 2, 6) X(0, 1, 6) X(0, 3, 6) X(1, 2, 7) X(0, 2, 7) X(3, 2, 7) X(0, 1, 7) X(0, 3, 7)
+
+hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
+#define X(S, R, ID)                                                                                        \
+  if (kp.shape == S && kp.rd == R && tile_id == ID) {                                                      \
+    hipLaunchKernelGGL((k_local_stream<S, R, stream_local_rows(ID)>), dim3(grid), dim3(kLanes), 0, s, src, \
+                       kp);                                                                                \
+    return hipGetLastError();                                                                              \
+  }
+  IPB_STREAM_LOCAL(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
+  if (tile_id == 5) hipLaunchKernelGGL((k_global_stream<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 6) hipLaunchKernelGGL((k_global_stream<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 7) hipLaunchKernelGGL((k_global_stream<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
+  // two steps over the queue of quarters: the fill values, then the second pass
+  if (tile_id == 5) hipLaunchKernelGGL((k_fill_pixels<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 6) hipLaunchKernelGGL((k_fill_pixels<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 7) hipLaunchKernelGGL((k_fill_pixels<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else return hipErrorInvalidValue;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (tile_id == 5) hipLaunchKernelGGL((k_global_patched<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 6) hipLaunchKernelGGL((k_global_patched<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else hipLaunchKernelGGL((k_global_patched<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  return hipGetLastError();
+}
+
+int stream_resident_blocks(int phase, int tile_id, const KParams& kp) {
+  if (phase == 1) {
+#define X(S, R, ID) \
+  if (kp.shape == S && kp.rd == R && tile_id == ID) return occupancy_s(k_local_stream<S, R, stream_local_rows(ID)>);
+    IPB_STREAM_LOCAL(X)
+#undef X
+    return 1;
+  }
+  if (tile_id == 5) return occupancy_s(k_global_stream<64>);
+  if (tile_id == 6) return occupancy_s(k_global_stream<32>);
+  if (tile_id == 7) return occupancy_s(k_global_stream<128>);
+  return 1;
+}
+
+}  // namespace ipb

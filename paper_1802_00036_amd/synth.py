@@ -145,6 +145,29 @@ def lidar_frame(H: int, W: int, *, seed: Sequence[int], n_rows: int = 64,
 # --------------------------------------------------------------------------
 # The five workloads (frames x size, scan rows, density, depth range).
 
+def config_frame(cfg: int, i: int, base: int = 0) -> Frame:
+    """Frame i of workload ``cfg`` (the same frame config_frames returns at i)."""
+    if cfg == 1:
+        return lidar_frame(352, 1216, seed=[1, 0, base], n_rows=64, density=0.05)
+    if cfg == 2:
+        dens = _rng([2, i, base, 99]).uniform(0.04, 0.06)
+        return lidar_frame(375, 1242, seed=[2, i, base], n_rows=64, density=dens)
+    if cfg == 3:
+        r = _rng([3, i, base, 99])
+        H = int(r.integers(256, 513))
+        W = int(r.integers(768, 2049))
+        rows = int(r.choice([32, 64, 128]))
+        dens = r.uniform(0.02, 0.10)
+        return lidar_frame(H, W, seed=[3, i, base], n_rows=rows, density=dens)
+    if cfg == 4:
+        return lidar_frame(1024, 4096, seed=[4, i, base], n_rows=128, density=0.03,
+                           d_max=120.0, occlusions=(4, 8))
+    raise ValueError(f"unknown workload {cfg}")
+
+
+CONFIG_SIZES = {1: 1, 2: 64, 3: 128, 4: 16}
+
+
 def config_frames(cfg: int, base: int = 0, limit: Optional[int] = None) -> List[Frame]:
     """Seeded frames of workload ``cfg``:
 
@@ -155,31 +178,10 @@ def config_frames(cfg: int, base: int = 0, limit: Optional[int] = None) -> List[
     4: 16 frames of 1024x4096, 128 scan rows, 3 % dense, 1-120 m, with 4-8
        occlusion rectangles and the empty sky above the top scan row.
     """
-    out: List[Frame] = []
-    if cfg == 1:
-        out.append(lidar_frame(352, 1216, seed=[1, 0, base], n_rows=64, density=0.05))
-    elif cfg == 2:
-        n = 64 if limit is None else min(64, limit)
-        for i in range(n):
-            dens = _rng([2, i, base, 99]).uniform(0.04, 0.06)
-            out.append(lidar_frame(375, 1242, seed=[2, i, base], n_rows=64, density=dens))
-    elif cfg == 3:
-        n = 128 if limit is None else min(128, limit)
-        for i in range(n):
-            r = _rng([3, i, base, 99])
-            H = int(r.integers(256, 513))
-            W = int(r.integers(768, 2049))
-            rows = int(r.choice([32, 64, 128]))
-            dens = r.uniform(0.02, 0.10)
-            out.append(lidar_frame(H, W, seed=[3, i, base], n_rows=rows, density=dens))
-    elif cfg == 4:
-        n = 16 if limit is None else min(16, limit)
-        for i in range(n):
-            out.append(lidar_frame(1024, 4096, seed=[4, i, base], n_rows=128, density=0.03,
-                                   d_max=120.0, occlusions=(4, 8)))
-    else:
+    if cfg not in CONFIG_SIZES:
         raise ValueError(f"unknown workload {cfg}")
-    return out
+    n = CONFIG_SIZES[cfg] if limit is None else min(CONFIG_SIZES[cfg], limit)
+    return [config_frame(cfg, i, base) for i in range(n)]
 
 
 SERVE_SIZES = ((352, 1216), (375, 1242), (512, 2048), (1024, 4096))

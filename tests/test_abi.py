@@ -149,7 +149,7 @@ def test_tile_table():
     lib = L.lib()
     for phase in (1, 2):
         n = lib.ipb_tile_count(phase)
-        assert n >= 4
+        assert n >= 7
         for t in range(1, n + 1):
             r, c = ctypes.c_int(), ctypes.c_int()
             assert lib.ipb_tile_shape(phase, t, ctypes.byref(r), ctypes.byref(c)) == 0

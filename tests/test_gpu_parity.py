@@ -122,8 +122,8 @@ def test_param_variants(i):
     assert_all_stages(synth.random_map(rng, 37, 70, 0.03, 1.0, 79.0), p, tag=f"variant {i} random")
 
 
-@pytest.mark.parametrize("tl", [1, 2, 3, 4])
-@pytest.mark.parametrize("tg", [1, 2, 3, 4])
+@pytest.mark.parametrize("tl", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tg", [1, 4, 5, 6, 7])
 def test_tile_shapes(tl, tg):
     p = api.Params(tile_local=tl, tile_global=tg)
     f = synth.lidar_frame(133, 290, seed=[12, tl, tg], n_rows=40, density=0.05)
