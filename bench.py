@@ -26,8 +26,13 @@ sys.path.insert(0, ROOT)
 METRIC = "frames/s and HBM GB/s at 375x1242 batched; p50/p99 latency under serving load"
 FRAMES, H, W = 64, 375, 1242
 HBM_PEAK_GBPS = 8000.0
-BYTES_PER_PX = {"ipb_local": 8, "ipb_global": 8}   # algorithmic bytes per pixel, per kernel
-KERNEL_SRC = os.path.join(ROOT, "paper_1802_00036_amd", "csrc", "kernels.hip")
+# launch steps of one batch (ipb_complete_planned phases 0..4) and the kernel each launches
+PHASES = ["k_reset", "k_local_stream", "k_global_stream", "k_fill_pixels+k_global_patched", "k_global_slow"]
+# algorithmic HBM bytes per pixel: stage-1 input read + stage-4 map write (phase 1);
+# stage-4 map read + output write (phase 2)
+BYTES_PER_PX = {"k_local_stream": 8, "k_global_stream": 8}
+CSRC = os.path.join(ROOT, "paper_1802_00036_amd", "csrc")
+KERNEL_SOURCES = ("common.hpp", "networks.hpp", "median_net.hpp", "kernels.hip", "stream.hip", "api.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_batched.json")
 
 
@@ -61,8 +66,13 @@ def cpu_baseline(n_frames: int = 64) -> dict:
 # ---------------------------------------------------------------- GPU part --
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the library sources, to tell whether committed counter
+    readings were taken on the current kernels."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(kernel: str):
@@ -86,6 +96,9 @@ def main() -> None:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-frame-steps", type=int, default=20)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain kernel reading and writing 256 MiB (calibrates rocprofv3 "
+                         "FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); frames are independent, so a "
@@ -138,20 +151,17 @@ def main() -> None:
         if evs is None:
             run_phase(st, -1)
             return
-        evs[0].record(stream)
-        run_phase(st, 0)
-        evs[1].record(stream)
-        run_phase(st, 1)
-        evs[2].record(stream)
-        run_phase(st, 2)
-        evs[3].record(stream)
+        for ph in range(len(PHASES)):
+            evs[ph].record(stream)
+            run_phase(st, ph)
+        evs[len(PHASES)].record(stream)
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
 
     # timed region: K steps, per-kernel HIP events on the launch stream
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -164,9 +174,7 @@ def main() -> None:
     wall = time.perf_counter() - w0
     total_ms = t_start.elapsed_time(t_end)
     ms_step = total_ms / args.steps
-    k_ms = {"ipb_reset": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
-            "ipb_local": float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
-            "ipb_global": float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))}
+    k_ms = {name: float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs])) for k, name in enumerate(PHASES)}
 
     # the plain per-frame path on the same frames (64 x ipb_complete_ws)
     st = sets[0]
@@ -192,9 +200,18 @@ def main() -> None:
         torch.cuda.synchronize()
         pf_ms = a.elapsed_time(b) / args.per_frame_steps
 
+    if args.copy_probe:
+        # a plain streaming kernel that reads 256 MiB and writes 256 MiB
+        src_t = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            torch.mul(src_t, 2.0, out=dst_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
+
     px = FRAMES * H * W
     fps = FRAMES / (ms_step / 1e3)
-    dom = max(("ipb_local", "ipb_global"), key=lambda k: k_ms[k])
+    dom = max(("k_local_stream", "k_global_stream"), key=lambda k: k_ms[k])
     achieved = BYTES_PER_PX[dom] * px / (k_ms[dom] / 1e3) / 1e9
     traffic = traffic_for(dom)
     rec = {

@@ -87,8 +87,10 @@ typedef struct {
  * Gaussian, offset 100).  p must not be NULL. */
 void ipb_params_default(ipb_params* p);
 
-/* Workspace bytes one frame of H x W needs (the stage-4 map and one int32 per
- * column).  Returns 0 for invalid sizes. */
+/* Workspace bytes one frame of H x W needs: the stage-4 map, a map for the
+ * large-fill values of cells left empty after the extension, one int32 per
+ * column and the queues of tiles that need the large fill.  Returns 0 for
+ * invalid sizes or parameters. */
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p);
 
 /* Complete one frame: depth_in (H x W, device) -> depth_out (H x W, device).
@@ -121,13 +123,17 @@ typedef struct {
   int32_t H, W;
 } ipb_frame;
 
-/* Workspace for a batch: a descriptor table, the stage-4 maps and the column
- * tables of all frames.  Returns 0 if any frame is invalid or n < 1. */
+/* Workspace for a batch: the launch plan, then per frame what
+ * ipb_workspace_bytes lists.  Returns 0 if any frame is invalid, two frames'
+ * outputs overlap another frame's buffers, or n < 1. */
 size_t ipb_batch_workspace_bytes(const ipb_frame* frames, int n, const ipb_params* p);
 
 /* Complete n frames (host array of descriptors with device pointers).  The
- * descriptor table is copied into the workspace with hipMemcpyAsync from the
- * caller's host array, which may be reused as soon as the call returns. */
+ * launch plan is built in a pinned staging buffer of the library and copied
+ * into the workspace on the stream (the staging buffer is reused only after
+ * that copy completed); the caller's array may be reused when the call
+ * returns.  Not capturable into a graph: use ipb_batch_plan and
+ * ipb_complete_planned for that. */
 int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p,
                        void* ws, size_t ws_bytes, void* stream);
 
@@ -144,12 +150,19 @@ int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p,
                    void* ws, size_t ws_bytes, void* plan_host, size_t plan_bytes);
 
 /* Run a planned batch.  plan_dev: device copy of a plan built by
- * ipb_batch_plan; max_frames, max_tiles_local/global and max_cols bound the
- * plans it may be replayed with (the launch grid is derived from them, so the
- * call can be captured once and replayed).  phase: -1 = all phases; 0 = only
- * the column-table reset; 1 = only stages 1-4; 2 = only stages 5-9 (phases
- * must run in order 0, 1, 2; the split exists for per-kernel timing).
- * Allocates nothing, synchronises nothing, reads no device memory on the host. */
+ * ipb_batch_plan with the same parameters p; max_tiles_local/global and
+ * max_cols bound the plans it may be replayed with (the launch grids are
+ * derived from them, so the call can be captured once and replayed).
+ * phase: -1 = everything; else one launch step, in this order:
+ *   0 reset the column tables and the tile queues;
+ *   1 stages 1-4;
+ *   2 stages 5-9 (streaming kernel: every tile, assuming the 31x31 fill
+ *     changes nothing; tile quarters where it does are queued);
+ *   3 the queued quarters: the fill at their empty cells, then stages 7-9
+ *     again (streaming kernels only; no-op otherwise);
+ *   4 tiles of frames under 3 rows or columns (streaming kernels only).
+ * The split exists for per-kernel timing.  Allocates nothing, synchronises
+ * nothing, reads no device memory on the host. */
 int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase,
                          int max_tiles_local, int max_tiles_global, int max_cols,
                          void* stream);

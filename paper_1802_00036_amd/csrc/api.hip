@@ -96,7 +96,7 @@ int resolve(const ipb_params* p, Resolved* r) {
   const bool ls_ok = stream_local_supported(k.shape, k.rd, k.rc, k.rf);
   const bool gs_ok = stream_global_supported(k.rm, k.rg);
   r->ltile = p->tile_local ? p->tile_local : (ls_ok ? 5 : 1);
-  r->gtile = p->tile_global ? p->tile_global : (gs_ok ? 5 : 1);
+  r->gtile = p->tile_global ? p->tile_global : (gs_ok ? 6 : 1);
   r->lstream = r->ltile >= 5;
   r->gstream = r->gtile >= 5;
   if ((r->lstream && !ls_ok) || (r->gstream && !gs_ok)) return IPB_ERR_UNSUPPORTED;
@@ -334,23 +334,24 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
     e = r.lstream ? launch_local_stream(src, kp, r.ltile, grid, s) : launch_local(src, kp, r.ltile, r.halo, grid, s);
     if (e != hipSuccess) return hip_fail(e);
   }
-  if ((phase == -1 || phase == 2) && last_stage >= 5) {
+  if (last_stage < 5) return IPB_OK;
+  if (phase == -1 || phase == 2) {
     int grid = max_gt;
     if (r.gstream) grid = (grid + 7) / 8 * 8;
     else if (persistent) grid = std::min(grid, resident(dev, 2, r.gtile, 0) * cus);
-    if (r.gstream) {
-      e = launch_global_stream(src, kp, r.gtile, grid, s);
-      if (e != hipSuccess) return hip_fail(e);
-      // queued quarters: at most four per tile; a grid of 32 waves per CU
-      const int rgrid = std::max(1, std::min(4 * max_gt, 32 * cus));
-      e = launch_global_repair(src, kp, r.gtile, rgrid, s);
-      if (e != hipSuccess) return hip_fail(e);
-      const int per = slow_subtiles(r.gth, r.gtw);
-      const int sgrid = std::max(1, std::min(max_gt * per, slow_res(dev) * cus));
-      e = launch_global_slow(src, kp, r.gth, r.gtw, sgrid, s);
-    } else {
-      e = launch_global(src, kp, r.gtile, grid, s);
-    }
+    e = r.gstream ? launch_global_stream(src, kp, r.gtile, grid, s) : launch_global(src, kp, r.gtile, grid, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if ((phase == -1 || phase == 3) && r.gstream) {
+    // queued quarters: at most four per tile; a grid of 32 waves per CU
+    const int rgrid = std::max(1, std::min(4 * max_gt, 32 * cus));
+    e = launch_global_repair(src, kp, r.gtile, rgrid, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if ((phase == -1 || phase == 4) && r.gstream) {
+    const int per = slow_subtiles(r.gth, r.gtw);
+    const int sgrid = std::max(1, std::min(max_gt * per, slow_res(dev) * cus));
+    e = launch_global_slow(src, kp, r.gth, r.gtw, sgrid, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   return IPB_OK;
@@ -477,7 +478,7 @@ int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase, i
   Resolved r;
   int st = resolve(p, &r);
   if (st != IPB_OK) return st;
-  if (plan_dev == nullptr || phase < -1 || phase > 2) return IPB_ERR_INVALID_ARG;
+  if (plan_dev == nullptr || phase < -1 || phase > 4) return IPB_ERR_INVALID_ARG;
   if (max_tiles_local < 1 || max_tiles_global < 1 || max_cols < 1) return IPB_ERR_INVALID_ARG;
   FrameSource src;
   std::memset(&src, 0, sizeof(src));
@@ -554,7 +555,7 @@ int ipb_last_hip_error(void) { return g_last_hip; }
 
 int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols) {
   if (rows == nullptr || cols == nullptr) return IPB_ERR_INVALID_ARG;
-  if (tile_id == 0) tile_id = 5;
+  if (tile_id == 0) tile_id = phase == 1 ? 5 : 6;   // defaults of the streaming kernels
   if (tile_id < 1 || tile_id > kTileIds) return IPB_ERR_INVALID_ARG;
   if (phase == 1) {
     *rows = tile_id >= 5 ? stream_local_tile_rows(tile_id) : local_tile_rows(tile_id);

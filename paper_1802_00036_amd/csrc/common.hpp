@@ -78,15 +78,23 @@ struct FrameSource {
 };
 
 // Queues of the streaming phase 2, in the workspace (cap = phase-2 tiles):
-//   slow[0]                 quarters (a tile id in the low 27 bits, the
-//                           quarter above) whose input rows still hold an
-//                           empty cell after the extension: they need the
-//                           31x31 fill (k_fill_pixels, then a second pass);
-//   slow[1]                 tiles of frames under 3 rows or columns,
-//                           recomputed by the LDS kernel;
-//   slow[2 .. 2+4cap)       the first queue, slow[2+4cap .. 2+5cap) the second.
-__host__ __device__ inline size_t slow_queue_ints(int cap) { return 2 + 5 * (size_t)cap; }
-__host__ __device__ inline int lds_queue_offset(int cap) { return 2 + 4 * cap; }
+//   slow[0]   quarters whose input rows still hold an empty cell after the
+//             extension and whose own rows hold at most kDenseEmpty empty
+//             cells: the 31x31 fill is computed per cell (k_fill_pixels);
+//   slow[2]   such quarters with more empty cells: the fill is computed
+//             separably for the whole quarter (k_fill_dense);
+//             entries of both: two ints, the frame index and the tile index
+//             within the frame with the quarter in bits 27..28; both queues
+//             then run again (k_global_patched);
+//   slow[1]   tiles of frames under 3 rows or columns (launch tile ids),
+//             recomputed by the LDS kernel;
+//   slow[4 ..)              the first queue (8 cap ints), then the dense
+//                           queue (8 cap ints), then the tiny-frame queue (cap).
+constexpr int kDenseEmpty = 32;
+__host__ __device__ inline size_t slow_queue_ints(int cap) { return 4 + 17 * (size_t)cap; }
+__host__ __device__ inline int sparse_queue_offset(int) { return 4; }
+__host__ __device__ inline int dense_queue_offset(int cap) { return 4 + 8 * cap; }
+__host__ __device__ inline int lds_queue_offset(int cap) { return 4 + 16 * cap; }
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_reset(const FrameSource& src, int max_cols, hipStream_t s);

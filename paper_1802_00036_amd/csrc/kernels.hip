@@ -603,7 +603,7 @@ __global__ __launch_bounds__(kThreads) void k_reset(FrameSource src) {
   int32_t* base = src.plan ? src.plan->top_base : src.single.top;
   const int n = src.plan ? src.plan->ncols : src.single.W;
   int32_t* slow = src.plan ? src.plan->slow : src.slow;
-  if (blockIdx.x == 0 && threadIdx.x < 2 && slow != nullptr) slow[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 4 && slow != nullptr) slow[threadIdx.x] = 0;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) base[i] = kNoTop;
 }
 

@@ -347,8 +347,8 @@ __device__ __forceinline__ double hsum5(double wc, double w1, double w2, int m2,
 // true, one quarter): cells empty after stage 5 read their stage-6 value
 // from f.v6p (written by k_fill_pixels).
 template <int TH, bool PATCHED>
-__device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int ty0, int tx0, int lane,
-                                   int32_t* slow, int cap) {
+__device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int fidx, int gt, int ty0, int tx0,
+                                   int lane, int32_t* slow, int cap) {
   const int H = f.H, W = f.W;
   const float thr = kp.thr, off = kp.off;
   const int kthr = key(thr);
@@ -409,8 +409,10 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) Sa[k] = Sb[k] = kInfKey;
-  // quarters (TH/4 output rows each) whose input rows (+-4) hold an empty cell
+  // quarters (TH/4 output rows each) whose input rows (+-4) hold an empty
+  // cell, and the number of empty cells in each quarter's own rows
   unsigned qmask = 0;
+  int qempty[4] = {0, 0, 0, 0};
 
   // Stage 5 on load: rows of the stage-4 map (border rows replicated), the
   // extension applied; fetched 8 rows ahead of their use.
@@ -444,11 +446,15 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
       fetch(r + 8, pa[u], pb[u]);
       if (q >= 0 && q < H) {
         if (!PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
-          // row q is an input row of quarter k when 16k - 4 <= q - ty0 < 16k + 20 (TH/4 = 16)
+          // row q is an input row of quarter k when k*QR - 4 <= q - ty0 < (k+1)*QR + 4
           const int rel = q - ty0;
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             if (rel >= k * (TH / 4) - 4 && rel < (k + 1) * (TH / 4) + 4) qmask |= 1u << k;
+          if (rel >= 0 && rel < TH) {
+            const int n_e = __popcll(__ballot(outa && va <= kthr)) + __popcll(__ballot(outb && vb <= kthr));
+            qempty[rel / (TH / 4)] += n_e;
+          }
         }
         if ((last == 5 || last == 6) && q >= ty0 && q < ty0 + TH) {
           gint* o = out + (size_t)q * W;
@@ -555,10 +561,14 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
   // Those quarters need the 31x31 fill: queue them (tile id in the low 27
   // bits, quarter above).
   if (!PATCHED && kp.extrapolate && qmask != 0 && lane == 0) {
-    const int base = atomicAdd(slow, __popc(qmask));
-    int k = 0;
     for (int qk = 0; qk < 4; ++qk)
-      if ((qmask >> qk) & 1u) slow[2 + base + k++] = t | (qk << 27);
+      if ((qmask >> qk) & 1u) {
+        const bool dense = qempty[qk] > kDenseEmpty;
+        const int pos = atomicAdd(slow + (dense ? 2 : 0), 1);
+        int32_t* e = slow + (dense ? dense_queue_offset(cap) : sparse_queue_offset(cap)) + 2 * pos;
+        e[0] = fidx;
+        e[1] = gt | (qk << 27);
+      }
   }
 }
 
@@ -570,12 +580,17 @@ __global__ __launch_bounds__(kLanes) void k_global_stream(FrameSource src, KPara
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
   for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
     FrameDesc f;
-    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[find_frame_s<false>(src.plan, t)];
-    else f = src.single;
+    int fidx = 0;
+    if (src.plan) {
+      fidx = find_frame_s<false>(src.plan, t);
+      f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx];
+    } else {
+      f = src.single;
+    }
     f = uniform_frame(f);
     const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
-    global_stream_tile<TH, false>(f, kp, t, tr * TH, (gt - tr * f.gcols) * kGlobalTW, lane, slow, cap);
+    global_stream_tile<TH, false>(f, kp, t, fidx, gt, tr * TH, (gt - tr * f.gcols) * kGlobalTW, lane, slow, cap);
   }
 }
 
@@ -601,15 +616,13 @@ __global__ __launch_bounds__(kLanes) void k_fill_pixels(FrameSource src, KParams
   const int dy = (lane >> 1) - rl;
   const bool lrow = (lane >> 1) < 2 * rl + 1;
   const int c_lo = -rl + 16 * (lane & 1), c_hi = min(rl, c_lo + 15);
+  const int32_t* queue = slow + sparse_queue_offset(0);
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
-    const int entry = slow[2 + i];
-    const int t = entry & ((1 << 27) - 1), qk = (unsigned)entry >> 27;
-    FrameDesc f;
-    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[find_frame_s<false>(src.plan, t)];
-    else f = src.single;
+    const int fidx = queue[2 * i], tq = queue[2 * i + 1];
+    const int gt = tq & ((1 << 27) - 1), qk = (unsigned)tq >> 27;
+    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
     f = uniform_frame(f);
     const int H = f.H, W = f.W;
-    const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
     const int y0 = tr * TH + qk * QR, tx0 = (gt - tr * f.gcols) * kGlobalTW;
     gcint* v4 = gc(f.v4);
@@ -674,6 +687,114 @@ __global__ __launch_bounds__(kLanes) void k_fill_pixels(FrameSource src, KParams
   }
 }
 
+// Van Herk/Gil-Werman running max of width 31: out[j] = max(a[j .. j+30])
+// for 32 outputs from 62 inputs (prefix maxima of one block, suffix maxima
+// of the other).
+__device__ __forceinline__ void vhgw31(const int* a, int* out) {
+  int suf[31], pre[31];
+  suf[30] = a[30];
+#pragma unroll
+  for (int k = 29; k >= 0; --k) suf[k] = max(a[k], suf[k + 1]);
+  pre[0] = a[31];
+#pragma unroll
+  for (int k = 1; k < 31; ++k) pre[k] = max(pre[k - 1], a[31 + k]);
+  out[0] = suf[0];
+#pragma unroll
+  for (int j = 1; j < 31; ++j) out[j] = max(suf[j], pre[j - 1]);
+  out[31] = pre[30];
+}
+
+// Phase 2, queued quarters with many empty cells, step 1: the same fill
+// values, computed separably for the whole quarter.  The stage-5 values of
+// the quarter's rows +- rl and columns +- rl go to LDS, their horizontal
+// window maxima (van Herk/Gil-Werman for the 31-wide window) to a second LDS
+// array, and each empty cell takes the vertical max of those.
+constexpr int kDW = kGlobalTW + 2 * kFillRad + 8;    // 158 staged columns (4 runs of 32 outputs + 30)
+
+template <int TH>
+__global__ __launch_bounds__(kLanes) void k_fill_dense(FrameSource src, KParams kp) {
+  constexpr int QR = TH / 4, SR = QR + 2 * kFillRad;
+  __shared__ int S[SR * kDW];
+  __shared__ int Hm[SR * 128];
+  const int lane = threadIdx.x;
+  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
+  const int count = slow[2];
+  const int32_t* queue = slow + dense_queue_offset(cap);
+  const int rl = kp.rl;
+  const int kthr = key(kp.thr);
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const int fidx = queue[2 * i], tq = queue[2 * i + 1];
+    const int gt = tq & ((1 << 27) - 1), qk = (unsigned)tq >> 27;
+    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
+    f = uniform_frame(f);
+    const int H = f.H, W = f.W;
+    const int tr = gt / f.gcols;
+    const int y0 = tr * TH + qk * QR, tx0 = (gt - tr * f.gcols) * kGlobalTW;
+    gcint* v4 = gc(f.v4);
+    gcint* top = gc(f.top);
+    gint* v6p = gw(f.v6p);
+    const int sr = QR + 2 * rl;
+    __syncthreads();                                    // LDS of the previous quarter is no longer read
+    // stage-5 values: window column cc = lane + 64 j, rows y0 - rl ..
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int cc = lane + 64 * j;
+      if (cc < kDW) {
+        const int gx = tx0 - rl + cc;
+        const bool colin = gx >= 0 && gx < W;
+        const int x = clampi_s(gx, 0, W - 1);
+        const int tt = kp.extrapolate ? top[x] : H;
+#pragma unroll 8
+        for (int rr = 0; rr < sr; ++rr) {
+          const int gy = y0 - rl + rr;
+          const int y = clampi_s(gy, 0, H - 1);
+          const int v = v4[(size_t)(tt < H ? max(y, tt) : y) * W + x];
+          S[rr * kDW + cc] = (colin && gy >= 0 && gy < H) ? v : 0;
+        }
+      }
+    }
+    __syncthreads();
+    // horizontal window maxima of the 128 (>= 120) quarter columns
+    for (int w = lane; w < sr * 4; w += kLanes) {
+      const int rr = w >> 2, j0 = (w & 3) * 32;
+      if (rl == kFillRad) {
+        int a[62], o[32];
+#pragma unroll
+        for (int c = 0; c < 62; ++c) a[c] = S[rr * kDW + j0 + c];
+        vhgw31(a, o);
+#pragma unroll
+        for (int c = 0; c < 32; ++c) Hm[rr * 128 + j0 + c] = o[c];
+      } else {
+        for (int c = 0; c < 32; ++c) {
+          const int* p = S + rr * kDW + j0 + c;
+          int m = p[0];
+          for (int d = 1; d <= 2 * rl; ++d) m = max(m, p[d]);
+          Hm[rr * 128 + j0 + c] = m;
+        }
+      }
+    }
+    __syncthreads();
+    // vertical max at the empty cells of the quarter's own rows
+    const int ca = 2 * lane;                            // lanes 0..59: quarter columns ca, ca + 1
+    if (lane < 60) {
+      for (int r = 0; r < QR && y0 + r < H; ++r) {
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int c = ca + s2, gx = tx0 + c;
+          if (gx >= W) continue;
+          const int v = S[(r + rl) * kDW + c + rl];
+          if (v > kthr) continue;
+          int m = v;
+          const int* p = Hm + r * 128 + c;
+          for (int d = 0; d <= 2 * rl; ++d) m = max(m, p[d * 128]);
+          v6p[(size_t)(y0 + r) * W + gx] = m;
+        }
+      }
+    }
+  }
+}
+
 // Phase 2, queued quarters, step 2: median, blur and output inversion of
 // the quarter again, with the stage-6 values of step 1.
 template <int TH>
@@ -681,18 +802,19 @@ __global__ __launch_bounds__(kLanes) void k_global_patched(FrameSource src, KPar
   constexpr int QR = TH / 4;
   const int lane = threadIdx.x;
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
-  const int count = slow[0];
+  const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
+  const int n_sparse = slow[0], count = n_sparse + slow[2];
   if (kp.last_stage == 5) return;                   // the stage-5 map needs no second pass
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
-    const int entry = slow[2 + i];
-    const int t = entry & ((1 << 27) - 1), qk = (unsigned)entry >> 27;
-    FrameDesc f;
-    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[find_frame_s<false>(src.plan, t)];
-    else f = src.single;
+    const int32_t* e = i < n_sparse ? slow + sparse_queue_offset(cap) + 2 * i
+                                    : slow + dense_queue_offset(cap) + 2 * (i - n_sparse);
+    const int fidx = e[0], tq = e[1];
+    const int gt = tq & ((1 << 27) - 1), qk = (unsigned)tq >> 27;
+    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
     f = uniform_frame(f);
-    const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
-    global_stream_tile<QR, true>(f, kp, t, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane, nullptr, 0);
+    global_stream_tile<QR, true>(f, kp, 0, fidx, gt, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane,
+                                 nullptr, 0);
   }
 }
 
@@ -746,12 +868,18 @@ hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int t
 }
 
 hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
-  // two steps over the queue of quarters: the fill values, then the second pass
+  // the fill values of the queued quarters (per cell, then separably for the
+  // dense ones), then the second pass over both queues
   if (tile_id == 5) hipLaunchKernelGGL((k_fill_pixels<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else if (tile_id == 6) hipLaunchKernelGGL((k_fill_pixels<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else if (tile_id == 7) hipLaunchKernelGGL((k_fill_pixels<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (tile_id == 5) hipLaunchKernelGGL((k_fill_dense<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 6) hipLaunchKernelGGL((k_fill_dense<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else hipLaunchKernelGGL((k_fill_dense<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (tile_id == 5) hipLaunchKernelGGL((k_global_patched<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else if (tile_id == 6) hipLaunchKernelGGL((k_global_patched<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
