@@ -1,13 +1,21 @@
-"""Benchmark: frames/s and HBM GB/s of the batched completion of 64
-synthetic LIDAR-shaped 375x1242 depth maps on one MI355X.
+"""Benchmark of the depth-completion chain on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 
-One step = one batch of 64 frames through all nine stages (three launches:
-column-table reset, stages 1-4, stages 5-9).  Inputs are resident in HBM;
-three buffer sets (input, output, workspace; ~357 MB each) are rotated so the
-256 MB Infinity Cache cannot serve a step from the previous one.  Prints one
-JSON line.
+Workloads (seeded synthetic LIDAR-shaped sparse depth maps, float32):
+  c2 (default)  64 x 375x1242, 4-6 % valid, one batched launch per phase
+  c1            one 352x1216 frame: per-call latency
+  c3            128 frames of uneven sizes (H 256-512, W 768-2048), autotuned
+                tile shapes, the whole chain replayed as one HIP graph
+  c4            16 x 1024x4096, 3 % valid, 1-120 m, offset 140
+  c5            serving: Poisson arrivals at 500 / 2000 / 8000 frames/s of a
+                size mix (and 16000 as an overload point), continuous batching
+                against the plain per-frame path
+
+One step = one batch through all nine stages.  Inputs are resident in HBM;
+three buffer sets (input, output, workspace) are rotated so the 256 MB
+Infinity Cache cannot serve a step from the previous one.  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -24,7 +32,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "frames/s and HBM GB/s at 375x1242 batched; p50/p99 latency under serving load"
-FRAMES, H, W = 64, 375, 1242
 HBM_PEAK_GBPS = 8000.0
 # launch steps of one batch (ipb_complete_planned phases 0..4) and the kernel each launches
 PHASES = ["k_reset", "k_local_stream", "k_global_stream", "k_fill_pixels+k_global_patched", "k_global_slow"]
@@ -34,33 +41,66 @@ BYTES_PER_PX = {"k_local_stream": 8, "k_global_stream": 8}
 CSRC = os.path.join(ROOT, "paper_1802_00036_amd", "csrc")
 KERNEL_SOURCES = ("common.hpp", "networks.hpp", "median_net.hpp", "kernels.hip", "stream.hip", "api.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_batched.json")
+PARAMS_TEXT = "diamond5 close5 fill7 extend fill31 median5 gauss5(binomial)"
+WORKLOADS = {
+    "c1": "one LIDAR-shaped sparse depth map, 352x1216 float32, 64 scan rows, 5 % valid, 1-80 m; per-call latency",
+    "c2": "batch of 64 LIDAR-shaped sparse depth maps, 375x1242 float32, 64 scan rows, 4-6 % valid, 1-80 m; "
+          "one batched launch per phase",
+    "c3": "uneven batch of 128 LIDAR-shaped maps, H U{256..512} x W U{768..2048}, 32/64/128 scan rows, "
+          "2-10 % valid; autotuned tiles, one HIP graph replay per batch",
+    "c4": "16 LIDAR-shaped maps of 1024x4096, 128 scan rows, 3 % valid, 1-120 m (offset 140), empty sky "
+          "and occlusions; one batched launch per phase",
+    "c5": "serving: Poisson arrivals at 500/2000/8000 frames/s, sizes 352x1216/375x1242/512x2048/1024x4096 "
+          "(0.4/0.3/0.2/0.1), 2-10 % valid; device-resident inputs (no host transfer), continuous batching "
+          "against one ipb_complete_ws per request on one stream",
+}
 
 
 # ------------------------------------------------------------ CPU baseline --
 
-def _oracle_frame(i: int) -> float:
-    import numpy as np  # noqa: F401
+def _oracle_frame(task) -> float:
     import oracle
     from paper_1802_00036_amd import synth
-    f = synth.config_frame(2, i)
+    cfg, i = task
+    f = synth.config_frame(cfg, i)
+    p = oracle.Params(max_depth=140.0) if cfg == 4 else oracle.Params()
     t = time.perf_counter()
-    oracle.complete_map(f.sparse)
+    oracle.complete_map(f.sparse, p)
     return time.perf_counter() - t
 
 
-def cpu_baseline(n_frames: int = 64) -> dict:
-    """The CPU oracle over a bounded sample of the same workload (frames
-    0..n-1 of the 64-frame batch), one frame per task over a process pool.
-    Runs before anything touches the GPU."""
+def cpu_baseline(cfg: int, n_frames: int) -> dict:
+    """The CPU oracle over a bounded sample of the same workload (its first
+    n frames), one frame per task over a process pool.  Runs before anything
+    touches the GPU."""
     procs = max(1, min(16, os.cpu_count() or 1, n_frames))
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(procs) as pool:
-        per = pool.map(_oracle_frame, range(n_frames))
+        per = pool.map(_oracle_frame, [(cfg, i) for i in range(n_frames)])
     wall = time.perf_counter() - t0
-    return {"value": n_frames / wall, "unit": "frames/s", "cores": procs, "kind": "oracle",
-            "sample": f"{n_frames} of the 64 375x1242 frames, all nine stages, {procs} processes; "
+    return {"value": round(n_frames / wall, 2), "unit": "frames/s", "cores": procs, "kind": "oracle",
+            "sample": f"frames 0-{n_frames - 1} of the workload, all nine stages, {procs} processes; "
                       f"{sum(per):.1f} s of single-core oracle time ({sum(per) / n_frames:.3f} s/frame)"}
+
+
+def _serve_frame(task):
+    from paper_1802_00036_amd import synth
+    s, i = task
+    return synth.serve_frame(s, i).sparse
+
+
+def serve_pool_host(per_size: int) -> dict:
+    """Pre-generated frames of the serving mix (host), per size index."""
+    from paper_1802_00036_amd import synth
+    tasks = [(s, i) for s in range(len(synth.SERVE_SIZES)) for i in range(per_size)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
+        maps = pool.map(_serve_frame, tasks, chunksize=4)
+    out = {}
+    for (s, _), m in zip(tasks, maps):
+        out.setdefault(s, []).append(m)
+    return out
 
 
 # ---------------------------------------------------------------- GPU part --
@@ -75,9 +115,11 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str):
+def traffic_for(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
+    it was taken on the current kernel source and this workload."""
+    if workload != "c2":
+        return None
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -89,13 +131,261 @@ def traffic_for(kernel: str):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+class Batches:
+    """Rotating buffer sets of one batch (inputs, outputs, workspace, device plan)."""
+
+    def __init__(self, host_maps, params, n_sets=3):
+        import torch
+        from paper_1802_00036_amd import _lib as L
+        from paper_1802_00036_amd import api
+        self.L, self.api, self.torch = L, api, torch
+        self.lib = L.lib()
+        self.params = params
+        self.cp = params.to_c()
+        self.dev = torch.device("cuda:0")
+        self.n = len(host_maps)
+        self.shapes = [m.shape for m in host_maps]
+        self.px = sum(H * W for H, W in self.shapes)
+        self.sets = []
+        for _ in range(n_sets):
+            ins = [torch.from_numpy(m).to(self.dev) for m in host_maps]
+            outs = [torch.empty_like(t) for t in ins]
+            arr = api.frames_array(ins, outs)
+            nb = int(self.lib.ipb_batch_workspace_bytes(arr, self.n, ctypes.byref(self.cp)))
+            ws = api._workspace(nb, self.dev)
+            pb = int(self.lib.ipb_batch_plan_bytes(self.n))
+            plan_h = ctypes.create_string_buffer(pb)
+            L.check(self.lib.ipb_batch_plan(arr, self.n, ctypes.byref(self.cp), ctypes.c_void_p(ws.data_ptr()), nb,
+                                            plan_h, pb), "ipb_batch_plan")
+            n, lt, gt, cols = (ctypes.c_int() for _ in range(4))
+            self.lib.ipb_plan_totals(plan_h, ctypes.byref(n), ctypes.byref(lt), ctypes.byref(gt), ctypes.byref(cols))
+            plan_d = torch.frombuffer(bytearray(plan_h.raw), dtype=torch.uint8).to(self.dev)
+            self.sets.append(dict(ins=ins, outs=outs, ws=ws, plan=plan_d, lt=lt.value, gt=gt.value, cols=cols.value))
+        self.stream = torch.cuda.current_stream()
+        self.sh = ctypes.c_void_p(self.stream.cuda_stream)
+
+    def run_phase(self, st, phase):
+        self.L.check(self.lib.ipb_complete_planned(ctypes.c_void_p(st["plan"].data_ptr()), ctypes.byref(self.cp),
+                                                   phase, st["lt"], st["gt"], st["cols"], self.sh),
+                     "ipb_complete_planned")
+
+    def time_planned(self, steps, warmup):
+        """Mean ms per batch and per launch step, HIP events on the launch stream."""
+        torch = self.torch
+        for i in range(warmup):
+            self.run_phase(self.sets[i % len(self.sets)], -1)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(steps)]
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t0.record(self.stream)
+        for i in range(steps):
+            st = self.sets[i % len(self.sets)]
+            for ph in range(len(PHASES)):
+                evs[i][ph].record(self.stream)
+                self.run_phase(st, ph)
+            evs[i][len(PHASES)].record(self.stream)
+        t1.record(self.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        k_ms = {name: sum(e[k].elapsed_time(e[k + 1]) for e in evs) / steps for k, name in enumerate(PHASES)}
+        return t0.elapsed_time(t1) / steps, k_ms, wall
+
+    def time_graph(self, steps, warmup):
+        """Mean ms per batch through GraphBatch (plan rewrite + one graph replay)."""
+        torch = self.torch
+        from paper_1802_00036_amd.batch import GraphBatch
+        engines = [GraphBatch(self.shapes, self.params, device=self.dev) for _ in self.sets]
+        for i in range(max(warmup, 2 * len(self.sets))):
+            k = i % len(self.sets)
+            engines[k].run(self.sets[k]["ins"], self.sets[k]["outs"])
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        last = None
+        for i in range(steps):
+            k = i % len(self.sets)
+            # one engine per buffer set; engines run on their own streams, so
+            # chain them to keep batches in sequence
+            if last is not None:
+                engines[k].stream.wait_event(last)
+            last = engines[k].run(self.sets[k]["ins"], self.sets[k]["outs"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        return 1e3 * wall / steps, sum(e.replays for e in engines)
+
+    def time_per_frame(self, reps):
+        """Mean ms for the batch as one ipb_complete_ws call per frame."""
+        torch, api, L = self.torch, self.api, self.L
+        st = self.sets[0]
+        fws = api._workspace(max(api.workspace_bytes(H, W, self.params) for H, W in self.shapes), self.dev)
+        fnb = fws.numel()
+
+        def once():
+            for i, (H, W) in enumerate(self.shapes):
+                L.check(self.lib.ipb_complete_ws(ctypes.c_void_p(st["ins"][i].data_ptr()), H, W,
+                                                 ctypes.byref(self.cp), ctypes.c_void_p(st["outs"][i].data_ptr()),
+                                                 ctypes.c_void_p(fws.data_ptr()), fnb, self.sh), "ipb_complete_ws")
+        for _ in range(2):
+            once()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(self.stream)
+        for _ in range(reps):
+            once()
+        b.record(self.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+
+def roofline(k_ms, px, workload):
+    dom = max(BYTES_PER_PX, key=lambda k: k_ms[k])
+    achieved = BYTES_PER_PX[dom] * px / (k_ms[dom] / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom, workload)}
+
+
+def record(args, workload, value, unit, ms_step, extra, higher=True):
+    rec = {
+        "metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None if ms_step is None else round(ms_step, 5), "higher_is_better": higher,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS[workload], "id": workload, "params": PARAMS_TEXT},
+    }
+    rec.update(extra)
+    rec["paper_context"] = ("90 frames/s on an Intel Core i7-7700K CPU (Table 1, Sec. IV), KITTI frames; "
+                            "context only")
+    print(json.dumps(rec), flush=True)
+
+
+def bench_batch(args, workload, cpu, serve_host=None):
+    import torch
+    from paper_1802_00036_amd import api, synth
+    cfg = int(workload[1])
+    params = api.Params(max_depth=140.0) if cfg == 4 else api.Params()
+    maps = [f.sparse for f in synth.config_frames(cfg)]
+    extra = {}
+    if cfg == 3:
+        from paper_1802_00036_amd import autotune
+        probe = [torch.from_numpy(m).to("cuda:0") for m in maps]
+        report = []
+        params = autotune.tune(probe, params, reps=5, use_cache=False, report=report)
+        extra["autotune"] = {"tile_local": params.tile_local, "tile_global": params.tile_global,
+                             "candidates_us": [(r["phase"], r["tile"], None if r["us"] is None else round(r["us"], 1))
+                                               for r in report]}
+        del probe
+    b = Batches(maps, params)
+    ms_step, k_ms, wall = b.time_planned(args.steps, args.warmup)
+    fps = b.n / (ms_step / 1e3)
+    extra.update({
+        "config": None,
+        "roofline": roofline(k_ms, b.px, workload),
+        "cpu_baseline": cpu,
+        "hbm_gbps_algorithmic_pipeline": round(16 * b.px / (ms_step / 1e3) / 1e9, 1),
+        "kernel_ms": {k: round(v, 5) for k, v in k_ms.items()},
+        "wall_s": round(wall, 3),
+    })
+    g_ms, replays = b.time_graph(max(10, args.steps // 2), 4)
+    extra["graph_path"] = {"frames_per_s": round(b.n / (g_ms / 1e3), 1), "ms_per_batch": round(g_ms, 4),
+                           "replays": replays, "note": "host clock around plan rewrite + graph replay"}
+    if args.per_frame_steps > 0:
+        pf_ms = b.time_per_frame(args.per_frame_steps)
+        extra["per_frame_path"] = {"frames_per_s": round(b.n / (pf_ms / 1e3), 1), "ms_per_batch": round(pf_ms, 4)}
+    if serve_host is not None:
+        extra["serving"] = serving_runs(serve_host, rates=(2000,), seconds=args.serve_seconds, modes=("batched",))
+    cfgd = {"workload": WORKLOADS[workload], "id": workload, "frames": b.n, "pixels": b.px, "params": PARAMS_TEXT}
+    if cfg in (2, 4):
+        cfgd.update(H=b.shapes[0][0], W=b.shapes[0][1])
+    extra["config"] = cfgd
+    record(args, workload, round(fps, 1), "frames/s", ms_step, extra)
+
+
+def bench_latency(args, cpu):
+    import torch
+    from paper_1802_00036_amd import api, synth
+    from paper_1802_00036_amd.batch import GraphBatch
+    m = synth.config_frames(1)[0].sparse
+    x = torch.from_numpy(m).to("cuda:0")
+    out = torch.empty_like(x)
+    lat = {}
+    for name in ("per_call", "graph"):
+        if name == "graph":
+            gb = GraphBatch([m.shape])
+        times = []
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if name == "graph":
+                gb.run([x], [out]).synchronize()
+            else:
+                api.complete(x, out=out)
+                torch.cuda.synchronize()
+            if i >= args.warmup:
+                times.append(time.perf_counter() - t)
+        times.sort()
+        lat[name] = {"p50_ms": round(1e3 * times[len(times) // 2], 4),
+                     "p99_ms": round(1e3 * times[min(len(times) - 1, int(0.99 * len(times)))], 4)}
+    record(args, "c1", lat["graph"]["p50_ms"], "ms (p50 latency, host clock)", lat["graph"]["p50_ms"],
+           {"latency": lat, "cpu_baseline": cpu}, higher=False)
+
+
+def serving_runs(host_pool, rates, seconds, modes=("batched", "per_frame"), warmup_s=1.0):
+    import numpy as np
+    import torch
+    from paper_1802_00036_amd import api, serve, synth
+    dev = torch.device("cuda:0")
+    pool = {s: [torch.from_numpy(m).to(dev) for m in maps] for s, maps in host_pool.items()}
+    torch.cuda.synchronize()
+    p140 = api.Params(max_depth=140.0)
+    big = [i for i, (H, _) in enumerate(synth.SERVE_SIZES) if H >= 1024]
+    free, _ = torch.cuda.mem_get_info(dev)
+    budget = int(min(8 << 30, free // 4))
+    out = {}
+    for mode in modes:
+        for rate in rates:
+            n = int(rate * (seconds + warmup_s))
+            arrivals, sizes = synth.poisson_arrivals(rate, n)
+            frames = [pool[int(s)][i % len(pool[int(s)])] for i, s in enumerate(sizes)]
+            params = [p140 if int(s) in big else None for s in sizes]
+            if mode == "batched":
+                ex = serve.GraphExecutor(slots=3, max_batch=16)
+                ex.warm([((serve.default_bucket(synth.SERVE_SIZES[s]), serve._params_key(p140 if s in big else None)),
+                          p140 if s in big else None) for s in range(len(synth.SERVE_SIZES))])
+                srv = serve.Server(ex, mem_budget=budget, max_batch=16, keep_outputs=False)
+            else:
+                ex = serve.PerFrameExecutor()
+                srv = serve.Server(ex, mem_budget=budget, max_batch=1, keep_outputs=False)
+                for s in range(len(synth.SERVE_SIZES)):
+                    api.complete(pool[s][0], p140 if s in big else None)
+            torch.cuda.synchronize()
+            st = serve.run_trace(srv, frames, arrivals, params, warmup=warmup_s)
+            st = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+            st["offered_fps"] = rate
+            st["requests"] = n
+            out[f"{mode}@{rate}"] = st
+            print(f"[serve] {mode} {rate}/s: {st}", file=sys.stderr, flush=True)
+            del srv, ex
+            torch.cuda.synchronize()
+    return out
+
+
+def bench_serving(args, host_pool):
+    res = serving_runs(host_pool, rates=(500, 2000, 8000, 16000), seconds=args.serve_seconds)
+    top = res.get("batched@2000", {})
+    record(args, "c5", top.get("p99_ms"), "ms (p99 latency at 2000 frames/s offered)", None,
+           {"serving": res, "pool_frames_per_size": args.serve_pool, "cpu_baseline": None}, higher=False)
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--per-frame-steps", type=int, default=20)
+    ap.add_argument("--per-frame-steps", type=int, default=10)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated frames per size for serving")
+    ap.add_argument("--no-serving", action="store_true", help="c2: skip the serving summary")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain kernel reading and writing 256 MiB (calibrates rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE)")
@@ -104,144 +394,30 @@ def main() -> None:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); frames are independent, so a "
               "multi-GPU run would shard whole frames across devices with no exchange.", file=sys.stderr)
         sys.exit(2)
+    wl = args.workload
+    # host work that forks runs before the GPU is touched
+    n_cpu = {"c1": 1, "c2": 64, "c3": 128, "c4": 16}.get(wl)
+    cpu = None if (args.no_cpu_baseline or n_cpu is None) else cpu_baseline(int(wl[1]), n_cpu)
+    host_pool = None
+    if wl == "c5" or (wl == "c2" and not args.no_serving):
+        host_pool = serve_pool_host(args.serve_pool)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline()
-
-    import numpy as np
     import torch
-
-    from paper_1802_00036_amd import _lib as L
-    from paper_1802_00036_amd import api, synth
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    lib = L.lib()
-    params = api.Params()
-    cp = params.to_c()
-    frames = synth.config_frames(2)
-    host = np.stack([f.sparse for f in frames])
-    n_sets = 3
-    sets = []
-    for s in range(n_sets):
-        inp = torch.from_numpy(host).to(dev)
-        out = torch.empty_like(inp)
-        ins = [inp[i] for i in range(FRAMES)]
-        outs = [out[i] for i in range(FRAMES)]
-        arr = api.frames_array(ins, outs)
-        nb = int(lib.ipb_batch_workspace_bytes(arr, FRAMES, ctypes.byref(cp)))
-        ws = api._workspace(nb, dev)
-        pb = int(lib.ipb_batch_plan_bytes(FRAMES))
-        plan_h = ctypes.create_string_buffer(pb)
-        L.check(lib.ipb_batch_plan(arr, FRAMES, ctypes.byref(cp), ctypes.c_void_p(ws.data_ptr()), nb, plan_h, pb),
-                "ipb_batch_plan")
-        n, lt, gt, cols = (ctypes.c_int() for _ in range(4))
-        lib.ipb_plan_totals(plan_h, ctypes.byref(n), ctypes.byref(lt), ctypes.byref(gt), ctypes.byref(cols))
-        plan_d = torch.frombuffer(bytearray(plan_h.raw), dtype=torch.uint8).to(dev)
-        sets.append(dict(inp=inp, out=out, ws=ws, plan=plan_d, lt=lt.value, gt=gt.value, cols=cols.value,
-                         ins=ins, outs=outs))
-    stream = torch.cuda.current_stream()
-    sh = ctypes.c_void_p(stream.cuda_stream)
-
-    def run_phase(st, phase):
-        L.check(lib.ipb_complete_planned(ctypes.c_void_p(st["plan"].data_ptr()), ctypes.byref(cp), phase,
-                                         st["lt"], st["gt"], st["cols"], sh), "ipb_complete_planned")
-
-    def step(i, evs=None):
-        st = sets[i % n_sets]
-        if evs is None:
-            run_phase(st, -1)
-            return
-        for ph in range(len(PHASES)):
-            evs[ph].record(stream)
-            run_phase(st, ph)
-        evs[len(PHASES)].record(stream)
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-
-    # timed region: K steps, per-kernel HIP events on the launch stream
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(args.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    t_start.record(stream)
-    for i in range(args.steps):
-        step(i, evs[i])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    total_ms = t_start.elapsed_time(t_end)
-    ms_step = total_ms / args.steps
-    k_ms = {name: float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs])) for k, name in enumerate(PHASES)}
-
-    # the plain per-frame path on the same frames (64 x ipb_complete_ws)
-    st = sets[0]
-    fws = api._workspace(api.workspace_bytes(H, W, params), dev)
-    fnb = fws.numel()
-
-    def per_frame_batch():
-        for i in range(FRAMES):
-            L.check(lib.ipb_complete_ws(ctypes.c_void_p(st["ins"][i].data_ptr()), H, W, ctypes.byref(cp),
-                                        ctypes.c_void_p(st["outs"][i].data_ptr()), ctypes.c_void_p(fws.data_ptr()),
-                                        fnb, sh), "ipb_complete_ws")
-    pf_ms = None
-    if args.per_frame_steps > 0:
-        for _ in range(3):
-            per_frame_batch()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(args.per_frame_steps):
-            per_frame_batch()
-        b.record(stream)
-        torch.cuda.synchronize()
-        pf_ms = a.elapsed_time(b) / args.per_frame_steps
+    torch.cuda.set_device(0)
+    if wl == "c1":
+        bench_latency(args, cpu)
+    elif wl == "c5":
+        bench_serving(args, host_pool)
+    else:
+        bench_batch(args, wl, cpu, host_pool)
 
     if args.copy_probe:
         # a plain streaming kernel that reads 256 MiB and writes 256 MiB
-        src_t = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        src_t = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
         dst_t = torch.empty_like(src_t)
         for _ in range(3):
             torch.mul(src_t, 2.0, out=dst_t)
         torch.cuda.synchronize()
-        del src_t, dst_t
-
-    px = FRAMES * H * W
-    fps = FRAMES / (ms_step / 1e3)
-    dom = max(("k_local_stream", "k_global_stream"), key=lambda k: k_ms[k])
-    achieved = BYTES_PER_PX[dom] * px / (k_ms[dom] / 1e3) / 1e9
-    traffic = traffic_for(dom)
-    rec = {
-        "metric": METRIC,
-        "value": round(fps, 1),
-        "unit": "frames/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "batch of 64 LIDAR-shaped sparse depth maps, 375x1242 float32, 64 scan rows, "
-                               "4-6 % valid, 1-80 m; one batched launch per phase",
-                   "frames": FRAMES, "H": H, "W": W, "params": "diamond5 close5 fill7 extend fill31 median5 gauss5"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic},
-        "cpu_baseline": cpu,
-        "hbm_gbps_algorithmic_pipeline": round(16 * px / (ms_step / 1e3) / 1e9, 1),
-        "kernel_ms": {k: round(v, 5) for k, v in k_ms.items()},
-        "per_frame_path": None if pf_ms is None else
-        {"frames_per_s": round(FRAMES / (pf_ms / 1e3), 1), "ms_per_64_frames": round(pf_ms, 4)},
-        "wall_s": round(wall, 3),
-        "paper_context": "90 frames/s on an Intel Core i7-7700K CPU (Table 1, Sec. IV), KITTI frames; context only",
-    }
-    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

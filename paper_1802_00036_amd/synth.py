@@ -58,10 +58,11 @@ def _scene(rng: np.random.Generator, H: int, W: int, d_max: float) -> np.ndarray
         y0 = max(0, y_foot - bh)
         gx = rng.uniform(-0.02, 0.02)
         gy = rng.uniform(-0.01, 0.01)
-        yy, xx = np.mgrid[y0:y_foot + 1, x0:x0 + bw]
+        x1 = min(W, x0 + bw)                          # narrow frames clip the box
+        yy, xx = np.mgrid[y0:y_foot + 1, x0:x1]
         face = z_foot + gx * (xx - x0) + gy * (yy - y0)
         face = np.clip(face, 1.0, d_max)
-        region = depth[y0:y_foot + 1, x0:x0 + bw]
+        region = depth[y0:y_foot + 1, x0:x1]
         np.minimum(region, face, out=region)          # nearer surface wins
     return depth
 

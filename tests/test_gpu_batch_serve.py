@@ -1,0 +1,119 @@
+"""GPU tests of the batch engine (graph capture and replay), the tile
+autotuner and the serving loop, all through the C ABI: every result must be
+bit-identical to the same frame completed alone, which in turn equals the
+oracle (checked on a sample)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1802_00036_amd import api, autotune, batch, serve, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def bits(t):
+    return np.ascontiguousarray(t.detach().cpu().numpy()).view(np.uint32)
+
+
+def lidar(H, W, seed, density=0.05):
+    return torch.from_numpy(synth.lidar_frame(H, W, seed=seed, n_rows=min(64, H), density=density).sparse).to(DEV)
+
+
+def test_graph_replays_match_eager_across_batches():
+    rng = np.random.default_rng(21)
+    cap = [(300, 700)] * 6
+    gb = batch.GraphBatch(cap, device=torch.device(DEV))
+    batches = []
+    for b in range(5):
+        n = int(rng.integers(1, 7))
+        shapes = [(int(rng.integers(1, 301)), int(rng.integers(1, 701))) for _ in range(n)]
+        if b == 2:
+            shapes = [(1, 1), (2, 5), (300, 700)][:n] or [(1, 1)]
+        batches.append([lidar(H, W, [21, b, i]) for i, (H, W) in enumerate(shapes)])
+    batches.append(batches[0])                       # replay an earlier batch again
+    for b, frames in enumerate(batches):
+        print(f"[graph replay] batch {b}: {[tuple(f.shape) for f in frames]}", flush=True)
+        assert gb.fits([tuple(f.shape) for f in frames])
+        outs = gb(frames)
+        torch.cuda.synchronize()
+        # eager work between replays
+        junk = torch.randn(1 << 20, device=DEV)
+        junk.mul_(2.0).sum().item()
+        for f, o in zip(frames, outs):
+            want = api.complete(f)
+            torch.cuda.synchronize()
+            assert np.array_equal(bits(o), bits(want)), f"batch {b} frame {tuple(f.shape)}"
+    assert gb.replays >= 4
+    m = batches[1][0].cpu().numpy()
+    assert np.array_equal(bits(torch.from_numpy(oracle.complete_map(m))), bits(api.complete(batches[1][0])))
+
+
+def test_graph_batch_rejects_oversized_batches():
+    gb = batch.GraphBatch([(64, 128)] * 2, device=torch.device(DEV))
+    assert not gb.fits([(64, 128)] * 3)
+    assert not gb.fits([(65, 128)] * 2)
+    assert gb.fits([(65, 128)])                         # one larger frame within the two-frame totals
+    with pytest.raises(ValueError):
+        gb.run([torch.zeros((64, 128), device=DEV)] * 3)
+
+
+def test_graph_batch_uneven_workload_sample_equals_oracle():
+    frames = [torch.from_numpy(f.sparse).to(DEV) for f in synth.config_frames(3, limit=5)]
+    gb = batch.GraphBatch.for_batch(frames)
+    for rep in range(3):
+        outs = gb(frames)
+        torch.cuda.synchronize()
+        for i, (f, o) in enumerate(zip(frames, outs)):
+            if rep == 0 and i < 2:
+                want = oracle.complete_map(f.cpu().numpy())
+                assert np.array_equal(bits(o), np.asarray(want, np.float32).view(np.uint32))
+            assert np.array_equal(bits(o), bits(api.complete(f)))
+
+
+def test_autotune_picks_a_valid_pair_and_results_do_not_change(tmp_path, monkeypatch):
+    monkeypatch.setenv("IPB_TUNE_CACHE", str(tmp_path / "tune.json"))
+    frames = [lidar(int(h), int(w), [22, i]) for i, (h, w) in enumerate([(256, 800), (300, 1100), (512, 2000)])]
+    report = []
+    p = autotune.tune(frames, reps=2, report=report)
+    assert 1 <= p.tile_local <= 7 and 1 <= p.tile_global <= 7
+    assert any(r["us"] is not None for r in report)
+    again = autotune.tune(frames, reps=2)              # from the cache
+    assert (again.tile_local, again.tile_global) == (p.tile_local, p.tile_global)
+    outs = api.complete_batch(frames, p)
+    for f, o in zip(frames, outs):
+        assert np.array_equal(bits(o), bits(api.complete(f)))
+
+
+@pytest.mark.parametrize("executor", ["graph", "per_frame"])
+def test_served_results_equal_alone(executor):
+    rng = np.random.default_rng(23)
+    shapes = [(352, 1216), (375, 1242), (200, 640), (96, 333)]
+    p140 = api.Params(max_depth=140.0)
+    frames, params = [], []
+    for i in range(40):
+        H, W = shapes[int(rng.integers(len(shapes)))]
+        frames.append(lidar(H, W, [23, i], density=float(rng.uniform(0.02, 0.1))))
+        params.append(p140 if i % 5 == 0 else None)
+    if executor == "graph":
+        ex = serve.GraphExecutor(slots=3, max_batch=4)
+    else:
+        ex = serve.PerFrameExecutor()
+    srv = serve.Server(ex, mem_budget=256 << 20, max_batch=4 if executor == "graph" else 1)
+    arrivals = np.cumsum(rng.exponential(1 / 4000.0, len(frames)))
+    stats = serve.run_trace(srv, frames, arrivals, params)
+    torch.cuda.synchronize()
+    print(f"[serve {executor}] {stats}", flush=True)
+    assert stats["completed"] == len(frames) and stats["rejected"] == 0
+    by_id = {r.rid: r for r in srv.done}
+    for i, f in enumerate(frames):
+        alone = api.complete(f, params[i] or api.Params())
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(by_id[i].out), bits(alone)), f"request {i}"
+    if executor == "graph":
+        assert ex.tiers == [1, 4]
+        assert {len(eng.capacity) for eng in ex.engines.values()} <= {1, 4}

@@ -1,0 +1,229 @@
+"""Host-side tests of the serving scheduler and the batch helpers (no GPU):
+admission by memory budget, size buckets, continuous batching over slots,
+rejection, statistics, and the autotuner's cache."""
+import collections
+import dataclasses
+import json
+
+import numpy as np
+import pytest
+
+from paper_1802_00036_amd import serve
+
+
+class FakeClock:
+    def __init__(self, step=1e-4):
+        self.t = 0.0
+        self.step = step
+
+    def __call__(self):
+        self.t += self.step
+        return self.t
+
+
+class FakeExecutor(serve.Executor):
+    """Batches finish after `polls` readiness checks; outputs are the
+    frames themselves.  Records how many batches were running at each launch."""
+
+    def __init__(self, slots=2, polls=3, in_order=False):
+        self.slots = slots
+        self.polls = polls
+        self.in_order = in_order
+        self.live = 0
+        self.launches = []          # (slot, bucket, rids, batches running after this launch)
+
+    def launch(self, slot, bucket, reqs):
+        self.live += 1
+        self.launches.append((slot, bucket, [r.rid for r in reqs], self.live))
+        return {"left": self.polls, "outs": [r.frame for r in reqs], "slot": slot}
+
+    def ready(self, h):
+        h["left"] -= 1
+        if h["left"] <= 0 and not h.get("counted"):
+            h["counted"] = True
+            self.live -= 1
+        return h["left"] <= 0
+
+    def outputs(self, h):
+        return h["outs"]
+
+    def recycle(self, outs):
+        self.recycled = getattr(self, "recycled", 0) + len(outs)
+
+
+class Frame:
+    def __init__(self, H, W, tag):
+        self.shape = (H, W)
+        self.tag = tag
+
+
+def make_server(slots=2, polls=3, budget=10**9, max_batch=4, max_queue=1000, in_order=False, keep=True):
+    ex = FakeExecutor(slots, polls, in_order)
+    return serve.Server(ex, mem_budget=budget, max_batch=max_batch, max_queue=max_queue, clock=FakeClock(),
+                        keep_outputs=keep), ex
+
+
+def test_every_request_completes_once_with_its_own_output():
+    srv, ex = make_server()
+    shapes = [(352, 1216), (375, 1242), (512, 2048), (1024, 4096)]
+    rng = np.random.default_rng(0)
+    reqs = [srv.submit(Frame(*shapes[int(rng.integers(4))], i)) for i in range(57)]
+    srv.drain()
+    assert all(r.status == "done" for r in reqs)
+    assert sorted(r.rid for r in srv.done) == list(range(57))
+    assert all(r.out.tag == r.rid for r in reqs)
+    assert srv.in_use == sum(r.nbytes for r in reqs)      # kept outputs stay counted until released
+    for r in reqs:
+        srv.release(r)
+    assert srv.in_use == 0
+
+
+def test_batches_are_bucketed_fifo_and_bounded():
+    srv, ex = make_server(max_batch=3)
+    shapes = [(352, 1216), (375, 1242), (300, 1200)]     # buckets: 384x1216, 384x1280, 320x1216
+    for i in range(30):
+        srv.submit(Frame(*shapes[i % 3], i))
+    srv.drain()
+    by_rid = {r.rid: r for r in srv.done}
+    for slot, bucket, rids, _ in ex.launches:
+        assert 1 <= len(rids) <= 3
+        assert len({by_rid[i].bucket for i in rids}) == 1
+        assert rids == sorted(rids)
+    # within a bucket, launches follow arrival order
+    seen = collections.defaultdict(list)
+    for _, bucket, rids, _ in ex.launches:
+        seen[bucket].extend(rids)
+    for rids in seen.values():
+        assert rids == sorted(rids)
+
+
+def test_default_bucket_rounds_up_to_64():
+    assert serve.default_bucket((375, 1242)) == (384, 1280)
+    assert serve.default_bucket((64, 64)) == (64, 64)
+    assert serve.default_bucket((1, 1)) == (64, 64)
+
+
+def test_continuous_batching_overlaps_slots():
+    srv, ex = make_server(slots=3, polls=50, max_batch=2)
+    for i in range(4):
+        srv.submit(Frame(64, 64, i))
+    srv.step()                                  # two batches of two start at once
+    for i in range(4, 6):
+        srv.submit(Frame(64, 64, i))
+    srv.step()                                  # arrivals start on the third slot while the others run
+    assert max(l[3] for l in ex.launches) == 3
+    srv.drain()
+    assert len(srv.done) == 6
+
+
+def test_memory_budget_bounds_admission():
+    frame_bytes = 4 * 100 * 100
+    srv, ex = make_server(slots=4, polls=5, budget=3 * frame_bytes, max_batch=8, keep=False)
+    for i in range(10):
+        srv.submit(Frame(100, 100, i))
+    srv.step()
+    assert srv.in_use == 3 * frame_bytes
+    assert len(srv.waiting) == 7
+    srv.drain()
+    assert srv.peak_in_use <= 3 * frame_bytes
+    assert len(srv.done) == 10 and not srv.rejected
+    assert ex.recycled == 10 and srv.in_use == 0
+
+
+def test_kept_outputs_hold_the_budget_until_released():
+    frame_bytes = 4 * 100 * 100
+    srv, ex = make_server(slots=2, polls=2, budget=2 * frame_bytes, max_batch=8)
+    reqs = [srv.submit(Frame(100, 100, i)) for i in range(4)]
+    with pytest.raises(RuntimeError):
+        srv.drain()                       # two outputs held, the next cannot be admitted
+    assert [r.status for r in reqs] == ["done", "done", "queued", "queued"]
+    srv.release(reqs[0])
+    srv.release(reqs[1])
+    assert srv.in_use == 0 and reqs[0].out is None and reqs[0].status == "released"
+    srv.release(reqs[0])                  # a second release changes nothing
+    assert srv.in_use == 0
+    srv.drain()
+    assert [r.status for r in reqs[2:]] == ["done", "done"]
+    assert srv.in_use == 2 * frame_bytes
+
+
+def test_rejections():
+    srv, _ = make_server(budget=4 * 64 * 64, max_queue=2)
+    big = srv.submit(Frame(128, 128, 0))                    # larger than the whole budget
+    assert big.status == "rejected"
+    a, b, c = (srv.submit(Frame(8, 8, i)) for i in range(3))   # queue holds two
+    assert (a.status, b.status, c.status) == ("queued", "queued", "rejected")
+    srv.drain()
+    assert srv.stats()["rejected"] == 2
+    assert srv.stats()["completed"] == 2
+
+
+def test_in_order_executor_polls_only_the_oldest():
+    srv, ex = make_server(slots=8, polls=2, max_batch=1, in_order=True)
+    for i in range(5):
+        srv.submit(Frame(16, 16, i))
+    srv.drain()
+    done_order = [r.rid for r in srv.done]
+    assert done_order == sorted(done_order)
+
+
+def test_stats_and_run_trace():
+    srv, _ = make_server(slots=2, polls=2, max_batch=4, keep=False)
+    frames = [Frame(64, 128, i) for i in range(40)]
+    arrivals = np.cumsum(np.full(40, 1e-3))
+    st = serve.run_trace(srv, frames, arrivals, warmup=0.0055)
+    assert st["completed"] == int(np.sum(arrivals >= 0.0055)) == 35
+    assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    assert st["wait_p99_ms"] >= 0 and 0 < st["service_p50_ms"] <= st["service_p99_ms"]
+    assert st["frames_per_batch"] >= 1
+    assert st["throughput_fps"] > 0
+    lat = [r.latency for r in srv.done]
+    assert min(lat) > 0
+
+
+def test_params_split_buckets():
+    @dataclasses.dataclass
+    class P:
+        max_depth: float = 100.0
+
+    srv, ex = make_server(max_batch=8)
+    for i in range(6):
+        srv.submit(Frame(64, 64, i), params=P(100.0 if i % 2 else 140.0))
+    srv.drain()
+    for _, bucket, rids, _ in ex.launches:
+        assert len({i % 2 for i in rids}) == 1
+
+
+# ---------------------------------------------------------------- autotune --
+
+def test_autotune_signatures_and_cache(tmp_path, monkeypatch):
+    from paper_1802_00036_amd import autotune
+    from paper_1802_00036_amd.api import Params
+    a = autotune.batch_signature([(375, 1242)] * 64)
+    b = autotune.batch_signature([(376, 1240)] * 64)
+    c = autotune.batch_signature([(375, 1242)] * 8)
+    assert a == b and a != c
+    assert autotune.params_signature(Params(tile_local=5)) == autotune.params_signature(Params(tile_global=3))
+    assert autotune.params_signature(Params()) != autotune.params_signature(Params(max_depth=140.0))
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("IPB_TUNE_CACHE", str(path))
+    assert autotune.cache_path() == str(path)
+    autotune._store_cache(str(path), "k1", {"tile_local": 5, "tile_global": 6})
+    autotune._store_cache(str(path), "k2", {"tile_local": 7, "tile_global": 5})
+    data = json.loads(path.read_text())
+    assert data["k1"]["tile_local"] == 5 and data["k2"]["tile_global"] == 5
+    path.write_text("not json")
+    assert autotune._load_cache(str(path)) == {}
+
+
+def test_shapes_workspace_bytes_matches_layout():
+    from paper_1802_00036_amd import batch
+    from paper_1802_00036_amd.api import Params
+    one = batch.shapes_workspace_bytes([(375, 1242)])
+    two = batch.shapes_workspace_bytes([(375, 1242), (375, 1242)])
+    assert two > one > 2 * 4 * 375 * 1242
+    assert two - one >= 2 * 4 * 375 * 1242
+    # larger frames never need less workspace
+    assert batch.shapes_workspace_bytes([(400, 1300)]) >= one
+    lt, gt, cols = batch._tile_counts(Params().to_c(), [(375, 1242), (64, 64)])
+    assert cols == 1306 and lt > 0 and gt > 0
