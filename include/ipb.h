@@ -23,7 +23,7 @@
  *
  * Conventions shared by every entry point:
  *   - Maps are float32, row-major, pitch = W, in DEVICE memory.  1 <= H, W and
- *     H * W < 2^31.
+ *     H * W <= 2^30 (the kernels address a map with 32-bit byte offsets).
  *   - Ownership: the caller owns every buffer (inputs, outputs, workspace) and
  *     keeps it alive until the stream work completes.  The library keeps no
  *     pointer after a call returns.
@@ -89,8 +89,8 @@ void ipb_params_default(ipb_params* p);
 
 /* Workspace bytes one frame of H x W needs: the stage-4 map, a map for the
  * large-fill values of cells left empty after the extension, one int32 per
- * column and the queues of tiles that need the large fill.  Returns 0 for
- * invalid sizes or parameters. */
+ * column and the queues of the tile quarters and cells that need the large
+ * fill.  Returns 0 for invalid sizes or parameters. */
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p);
 
 /* Complete one frame: depth_in (H x W, device) -> depth_out (H x W, device).

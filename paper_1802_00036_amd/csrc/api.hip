@@ -25,8 +25,10 @@ int hip_fail(hipError_t e) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// every byte offset within a map fits in 32 bits (the kernels address maps
+// with 32-bit offsets from the map's base)
 bool size_ok(int H, int W) {
-  return H >= 1 && W >= 1 && static_cast<long long>(H) * W < (1LL << 31);
+  return H >= 1 && W >= 1 && static_cast<long long>(H) * W <= (1LL << 30);
 }
 
 // Parameters resolved into what the kernels take.
@@ -343,9 +345,11 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
     if (e != hipSuccess) return hip_fail(e);
   }
   if ((phase == -1 || phase == 3) && r.gstream) {
-    // queued quarters: at most four per tile; a grid of 32 waves per CU
+    // queued quarters (at most four per tile) and cells (at most
+    // 4 kCellEmpty per tile); grids of at most 32 waves per CU
     const int rgrid = std::max(1, std::min(4 * max_gt, 32 * cus));
-    e = launch_global_repair(src, kp, r.gtile, rgrid, s);
+    const int cgrid = std::max(1, (int)std::min<long long>(4LL * kCellEmpty * max_gt, 32LL * cus));
+    e = launch_global_repair(src, kp, r.gtile, rgrid, cgrid, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   if ((phase == -1 || phase == 4) && r.gstream) {

@@ -79,22 +79,26 @@ struct FrameSource {
 
 // Queues of the streaming phase 2, in the workspace (cap = phase-2 tiles):
 //   slow[0]   quarters whose input rows still hold an empty cell after the
-//             extension and whose own rows hold at most kDenseEmpty empty
-//             cells: the 31x31 fill is computed per cell (k_fill_pixels);
+//             extension and whose own rows hold at most kCellEmpty empty
+//             cells (their cells go to the cell queue);
 //   slow[2]   such quarters with more empty cells: the fill is computed
 //             separably for the whole quarter (k_fill_dense);
 //             entries of both: two ints, the frame index and the tile index
 //             within the frame with the quarter in bits 27..28; both queues
 //             then run again (k_global_patched);
+//   slow[3]   cells of the first kind of quarter, each filled on its own
+//             (k_fill_cells): two ints, the frame index and y * W + x;
 //   slow[1]   tiles of frames under 3 rows or columns (launch tile ids),
 //             recomputed by the LDS kernel;
-//   slow[4 ..)              the first queue (8 cap ints), then the dense
-//                           queue (8 cap ints), then the tiny-frame queue (cap).
-constexpr int kDenseEmpty = 32;
-__host__ __device__ inline size_t slow_queue_ints(int cap) { return 4 + 17 * (size_t)cap; }
+//   slow[4 ..)              the first queue (8 cap ints), the dense queue
+//                           (8 cap ints), the tiny-frame queue (cap), then
+//                           the cell queue (8 kCellEmpty cap ints).
+constexpr int kCellEmpty = 32;
+__host__ __device__ inline size_t slow_queue_ints(int cap) { return 4 + (17 + 8 * kCellEmpty) * (size_t)cap; }
 __host__ __device__ inline int sparse_queue_offset(int) { return 4; }
 __host__ __device__ inline int dense_queue_offset(int cap) { return 4 + 8 * cap; }
 __host__ __device__ inline int lds_queue_offset(int cap) { return 4 + 16 * cap; }
+__host__ __device__ inline int cell_queue_offset(int cap) { return 4 + 17 * cap; }
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_reset(const FrameSource& src, int max_cols, hipStream_t s);
@@ -112,7 +116,8 @@ bool stream_local_supported(int shape, int rd, int rc, int rf);
 bool stream_global_supported(int rm, int rg);
 hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s);
 hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s);
-hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s);
+hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, int cell_grid,
+                                hipStream_t s);
 int stream_resident_blocks(int phase, int tile_id, const KParams& kp);
 hipError_t launch_local(const FrameSource& src, const KParams& kp, int tile_id, int halo,
                         int grid, hipStream_t s);

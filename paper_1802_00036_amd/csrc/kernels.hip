@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kThreads) void k_global_slow(FrameSource src, KPara
   __shared__ float s_topv[RW];
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
-  const int count = slow[1];
+  const int count = min(slow[1], cap);
   const int32_t* queue = slow + lds_queue_offset(cap);
   const int nsy = (srows + TH - 1) / TH, nsx = (scols + TW - 1) / TW, per = nsy * nsx;
   for (int i = blockIdx.x; i < count * per; i += gridDim.x) {

@@ -10,8 +10,10 @@
 //                     Gaussian, output inversion); 128 input columns -> 120
 //                     output columns.  A tile whose needed cells still hold an
 //                     empty pixel after the extension needs the 31x31 fill
-//                     (stage 6): its quarters are queued; k_fill_pixels
-//                     computes the fill at the empty cells and
+//                     (stage 6): its quarters are queued, and the empty
+//                     cells of quarters with few of them are queued one by
+//                     one; k_fill_cells (per cell) or k_fill_dense (per
+//                     quarter) computes the fill at the empty cells and
 //                     k_global_patched runs those quarters again.
 //
 // Border rules are the ones of the LDS kernels: morphology ignores cells
@@ -70,6 +72,16 @@ __device__ __forceinline__ int xcd_tile_s(int b, int g) {
 // The frame of a tile is the same for the whole wave: keep it in scalar
 // registers.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A register copy the compiler cannot fold away.  Taking a prefetched row
+// out of its ring slot this way lets the prefetch of row r + 8 load into the
+// slot's own register; otherwise the loop carries register copies of loads
+// still in flight, and every pass of the unrolled loop waits for all of them.
+__device__ __forceinline__ int detach(int v) {
+  int r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+__device__ __forceinline__ float detachf(float v) { return __int_as_float(detach(__float_as_int(v))); }
 template <class P>
 __device__ __forceinline__ P* uni_ptr(P* p) {
   const unsigned long long a = reinterpret_cast<unsigned long long>(p);
@@ -133,6 +145,11 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   const bool lane_out = lane >= kLocalHalo / 2 && lane < kLocalHalo / 2 + kLocalTW / 2;
   const bool outa = lane_out && ina, outb = lane_out && inb;
   const unsigned ua = 4u * (unsigned)ca, ub = ua + 4u;   // byte offsets, used only when in the image
+  // load offsets: columns clamped into the image, so that every load is
+  // issued unconditionally (the values of outside columns are masked where
+  // they are used); loads issued on every path let the compiler wait for
+  // each row alone instead of draining the prefetch
+  const unsigned la = 4u * (unsigned)clampi_s(ca, 0, W - 1), lb = 4u * (unsigned)clampi_s(cb, 0, W - 1);
   const int last = kp.last_stage;
   constexpr int D2 = RD, D3A = RD + 2, D3B = RD + 4, D4 = RD + 7;  // row delays of the stage outputs
   const int q0 = ty0 - D4;
@@ -160,14 +177,9 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   // input rows are fetched 8 rows ahead of their use
   float da[8], db[8];
   auto fetch = [&](int r, float& xa_, float& xb_) {
-    const int q = q0 + r;
-    xa_ = 0.f;
-    xb_ = 0.f;
-    if (r < n && q >= 0 && q < H) {
-      gcfloat* row = in + (size_t)q * W;
-      if (ina) xa_ = ldf(row, ua);
-      if (inb) xb_ = ldf(row, ub);
-    }
+    gcfloat* row = in + (size_t)clampi_s(q0 + r, 0, H - 1) * W;
+    xa_ = ldf(row, la);
+    xb_ = ldf(row, lb);
   };
 #pragma unroll
   for (int u = 0; u < 8; ++u) fetch(u, da[u], db[u]);
@@ -182,16 +194,13 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       // Stage 1: inversion of input row q.
       int va, vb;
       {
-        const float d0 = da[u], d1 = db[u];
+        const bool rin = q >= 0 && q < H;
+        const float x0 = detachf(da[u]), x1 = detachf(db[u]);
+        const float d0 = (rin && ina) ? x0 : 0.f, d1 = (rin && inb) ? x1 : 0.f;
         fetch(r + 8, da[u], db[u]);
         const float v0 = off - d0, v1 = off - d1;
         va = (d0 > thr && v0 > thr) ? key(v0) : 0;
         vb = (d1 > thr && v1 > thr) ? key(v1) : 0;
-      }
-      if (last == 1 && q >= ty0 && q < ty0 + TH && q < H) {
-        gint* o = dst + (size_t)q * W;
-        if (outa) stk(o, ua, va);
-        if (outb) stk(o, ub, vb);
       }
 
       // Stage 2: kernel dilation; horizontal maxima of row q, then the
@@ -220,11 +229,6 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       const bool row2 = p2 >= 0 && p2 < H;
       w2a = (row2 && ina) ? w2a : 0;
       w2b = (row2 && inb) ? w2b : 0;
-      if (last == 2 && p2 >= ty0 && p2 < ty0 + TH && p2 < H) {
-        gint* o = dst + (size_t)p2 * W;
-        if (outa) stk(o, ua, w2a);
-        if (outb) stk(o, ub, w2b);
-      }
 
       // Stage 3a: 5x5 dilation; horizontal max of stage-2 row p2.
       {
@@ -255,11 +259,6 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       eb = (row4 && inb) ? eb : 0;
       v3[u][0] = ea;
       v3[u][1] = eb;
-      if (last == 3 && p4 >= ty0 && p4 < ty0 + TH && p4 < H) {
-        gint* o = dst + (size_t)p4 * W;
-        if (outa) stk(o, ua, ea);
-        if (outb) stk(o, ub, eb);
-      }
 
       // Stage 4: 7x7 fill of empty pixels; horizontal max of row p4, then
       // the vertical max and the select for row p4 - 3.
@@ -271,23 +270,30 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         hf[u][1] = max(t, RRa);
       }
       const int o4 = q - D4;
-      if (last >= 4 && o4 >= ty0 && o4 < ty0 + TH && o4 < H) {
+      const bool o4row = o4 >= ty0 && o4 < ty0 + TH && o4 < H;
+      int oa = 0, ob = 0;
+      if (last >= 4 && o4row) {
         const int ma = max3i(max3i(hf[(u - 6) & 7][0], hf[(u - 5) & 7][0], hf[(u - 4) & 7][0]),
                              max3i(hf[(u - 3) & 7][0], hf[(u - 2) & 7][0], hf[(u - 1) & 7][0]), hf[u][0]);
         const int mb = max3i(max3i(hf[(u - 6) & 7][1], hf[(u - 5) & 7][1], hf[(u - 4) & 7][1]),
                              max3i(hf[(u - 3) & 7][1], hf[(u - 2) & 7][1], hf[(u - 1) & 7][1]), hf[u][1]);
         const int c3a = v3[(u - 3) & 7][0], c3b = v3[(u - 3) & 7][1];
-        const int oa = c3a <= kthr ? ma : c3a;
-        const int ob = c3b <= kthr ? mb : c3b;
-        gint* o = dst + (size_t)o4 * W;
-        if (outa) {
-          stk(o, ua, oa);
-          if (oa > kthr && first_a == kNoTop) first_a = o4;
-        }
-        if (outb) {
-          stk(o, ub, ob);
-          if (ob > kthr && first_b == kNoTop) first_b = o4;
-        }
+        oa = c3a <= kthr ? ma : c3a;
+        ob = c3b <= kthr ? mb : c3b;
+        if (outa && oa > kthr && first_a == kNoTop) first_a = o4;
+        if (outb && ob > kthr && first_b == kNoTop) first_b = o4;
+      }
+
+      // One store site per row, for the map of the last stage asked for
+      // (each extra site would add conditional stores to every row).
+      int srow = o4, sa = oa, sb = ob;
+      if (last == 1) { srow = q; sa = va; sb = vb; }
+      else if (last == 2) { srow = p2; sa = w2a; sb = w2b; }
+      else if (last == 3) { srow = p4; sa = ea; sb = eb; }
+      if (srow >= ty0 && srow < ty0 + TH && srow < H) {
+        gint* o = dst + (size_t)srow * W;
+        if (outa) stk(o, ua, sa);
+        if (outb) stk(o, ub, sb);
       }
     }
   }
@@ -345,17 +351,21 @@ __device__ __forceinline__ double hsum5(double wc, double w1, double w2, int m2,
 // (PATCHED false): the stage-6 map is taken to equal the stage-5 map; tiles
 // where that does not hold are queued by quarter.  Second pass (PATCHED
 // true, one quarter): cells empty after stage 5 read their stage-6 value
-// from f.v6p (written by k_fill_pixels).
+// from f.v6p (written by k_fill_cells / k_fill_dense).  s_cells: LDS lists
+// of the first kCellEmpty empty cells of each quarter (first pass only).
 template <int TH, bool PATCHED>
 __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int fidx, int gt, int ty0, int tx0,
-                                   int lane, int32_t* slow, int cap) {
+                                   int lane, int32_t* slow, int cap, int* s_cells) {
   const int H = f.H, W = f.W;
   const float thr = kp.thr, off = kp.off;
   const int kthr = key(thr);
   const int last = kp.last_stage;
   const bool median = kp.rm == 2;
   if (!PATCHED && (H < 3 || W < 3)) {   // reflect-101 on tiny frames: leave it to the LDS kernel
-    if (lane == 0) slow[lds_queue_offset(cap) + atomicAdd(slow + 1, 1)] = t;
+    if (lane == 0) {
+      const int pos = atomicAdd(slow + 1, 1);
+      if (pos < cap) slow[lds_queue_offset(cap) + pos] = t;
+    }
     return;
   }
   const int ca = tx0 - 4 + 2 * lane, cb = ca + 1;
@@ -369,13 +379,18 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
   gcint* v4 = gc(f.v4);
   gint* out = gw(f.out);
 
-  // Stage 5 (extension to top of frame): the row and value each column copies up.
-  int topa = 0, topb = 0, tva = 0, tvb = 0;
+  // Stage 5 (extension to top of frame) on load: a row above its column's
+  // top reads the top cell instead, V5[y][x] = V4[max(y, top)][x]; as byte
+  // offsets, the larger of the row's and the top cell's (0 without a top).
+  // Every load is issued unconditionally, so that the compiler waits for
+  // each row alone instead of draining the prefetch.
+  const unsigned W4 = 4u * (unsigned)W;
+  unsigned toffa = 0, toffb = 0;
   if (kp.extrapolate) {
     gcint* top = gc(f.top);
     const int t_a = top[xa], t_b = top[xb];
-    if (t_a < H) { topa = t_a; tva = v4[(size_t)t_a * W + xa]; }
-    if (t_b < H) { topb = t_b; tvb = v4[(size_t)t_b * W + xb]; }
+    if (t_a < H) toffa = (unsigned)t_a * W4 + oxa;
+    if (t_b < H) toffb = (unsigned)t_b * W4 + oxb;
   }
 
   // reflect-101 source lane/slot of this lane's columns, for the Gaussian's border
@@ -416,25 +431,21 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
 
   // Stage 5 on load: rows of the stage-4 map (border rows replicated), the
   // extension applied; fetched 8 rows ahead of their use.
-  int pa[8], pb[8];
+  // PATCHED: the stage-6 value of the same cell, used where the stage-5
+  // value is empty (such a cell is at or below its column's top).
+  int pa[8], pb[8], ppa[8], ppb[8];
   gcint* v6p = gc(f.v6p);
-  auto fetch = [&](int r, int& xa_, int& xb_) {
-    const int gy = clampi_s(q0 + r, 0, H - 1);
-    xa_ = tva;
-    xb_ = tvb;
-    if (r < n) {
-      gcint* row = v4 + (size_t)gy * W;
-      if (gy >= topa) xa_ = ldk(row, oxa);
-      if (gy >= topb) xb_ = ldk(row, oxb);
-      if (PATCHED) {
-        gcint* prow = v6p + (size_t)gy * W;
-        if (xa_ <= kthr) xa_ = ldk(prow, oxa);
-        if (xb_ <= kthr) xb_ = ldk(prow, oxb);
-      }
+  auto fetch = [&](int r, int u_) {
+    const unsigned rowoff = (unsigned)clampi_s(q0 + r, 0, H - 1) * W4;
+    pa[u_] = ldk(v4, max(rowoff + oxa, toffa));
+    pb[u_] = ldk(v4, max(rowoff + oxb, toffb));
+    if (PATCHED) {
+      ppa[u_] = ldk(v6p, rowoff + oxa);
+      ppb[u_] = ldk(v6p, rowoff + oxb);
     }
   };
 #pragma unroll
-  for (int u = 0; u < 8; ++u) fetch(u, pa[u], pb[u]);
+  for (int u = 0; u < 8; ++u) fetch(u, u);
 
   for (int rb = 0; rb < n; rb += 8) {
 #pragma unroll
@@ -442,8 +453,12 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
       const int r = rb + u;
       if (r >= n) break;
       const int q = q0 + r;
-      const int va = pa[u], vb = pb[u];
-      fetch(r + 8, pa[u], pb[u]);
+      int va = detach(pa[u]), vb = detach(pb[u]);
+      if (PATCHED) {
+        va = va <= kthr ? detach(ppa[u]) : va;
+        vb = vb <= kthr ? detach(ppb[u]) : vb;
+      }
+      fetch(r + 8, u);
       if (q >= 0 && q < H) {
         if (!PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
           // row q is an input row of quarter k when k*QR - 4 <= q - ty0 < (k+1)*QR + 4
@@ -452,8 +467,23 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
           for (int k = 0; k < 4; ++k)
             if (rel >= k * (TH / 4) - 4 && rel < (k + 1) * (TH / 4) + 4) qmask |= 1u << k;
           if (rel >= 0 && rel < TH) {
-            const int n_e = __popcll(__ballot(outa && va <= kthr)) + __popcll(__ballot(outb && vb <= kthr));
-            qempty[rel / (TH / 4)] += n_e;
+            // empty output cells of this row: count them per quarter and
+            // list the first kCellEmpty of each quarter (y * W + x)
+            const bool ea = outa && va <= kthr, eb = outb && vb <= kthr;
+            const unsigned long long ma = __ballot(ea), mb = __ballot(eb);
+            const unsigned long long below = (1ull << lane) - 1ull;
+            const int k = rel / (TH / 4);
+            int base = 0;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+              if (kk == k) base = qempty[kk];
+            const int ja = base + __popcll(ma & below), jb = base + __popcll(ma) + __popcll(mb & below);
+            if (ea && ja < kCellEmpty) s_cells[k * kCellEmpty + ja] = q * W + ca;
+            if (eb && jb < kCellEmpty) s_cells[k * kCellEmpty + jb] = q * W + cb;
+            const int n_e = __popcll(ma) + __popcll(mb);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+              if (kk == k) qempty[kk] += n_e;
           }
         }
         if ((last == 5 || last == 6) && q >= ty0 && q < ty0 + TH) {
@@ -556,24 +586,42 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
       }
     }
   }
-  // Cells the median and blur need still hold an empty pixel: this tile
-  // needs the 31x31 fill; queue it for the LDS kernel.
-  // Those quarters need the 31x31 fill: queue them (tile id in the low 27
-  // bits, quarter above).
-  if (!PATCHED && kp.extrapolate && qmask != 0 && lane == 0) {
-    for (int qk = 0; qk < 4; ++qk)
-      if ((qmask >> qk) & 1u) {
-        const bool dense = qempty[qk] > kDenseEmpty;
+  // Quarters whose median and blur inputs still hold an empty pixel need the
+  // 31x31 fill and a second pass: queue them (tile id in the low 27 bits,
+  // quarter above), and queue the empty cells of those with few of them.
+  if (!PATCHED && kp.extrapolate && qmask != 0) {
+    __syncthreads();                                 // the cell lists are complete
+    int32_t* cells = slow + cell_queue_offset(cap);
+    for (int qk = 0; qk < 4; ++qk) {
+      if (((qmask >> qk) & 1u) == 0) continue;
+      const int ne = qempty[qk];
+      const bool dense = ne > kCellEmpty;
+      // (the bounds hold when every tile is visited once after a reset; a
+      // repeated launch without one drops entries instead of overrunning)
+      if (lane == 0) {
         const int pos = atomicAdd(slow + (dense ? 2 : 0), 1);
-        int32_t* e = slow + (dense ? dense_queue_offset(cap) : sparse_queue_offset(cap)) + 2 * pos;
-        e[0] = fidx;
-        e[1] = gt | (qk << 27);
+        if (pos < 4 * cap) {
+          int32_t* e = slow + (dense ? dense_queue_offset(cap) : sparse_queue_offset(cap)) + 2 * pos;
+          e[0] = fidx;
+          e[1] = gt | (qk << 27);
+        }
       }
+      if (!dense && ne > 0) {
+        int pos = 0;
+        if (lane == 0) pos = atomicAdd(slow + 3, ne);
+        pos = __shfl(pos, 0);
+        if (lane < ne && pos + lane < 4 * kCellEmpty * cap) {
+          cells[2 * (pos + lane)] = fidx;
+          cells[2 * (pos + lane) + 1] = s_cells[qk * kCellEmpty + lane];
+        }
+      }
+    }
   }
 }
 
 template <int TH>
 __global__ __launch_bounds__(kLanes) void k_global_stream(FrameSource src, KParams kp) {
+  __shared__ int s_cells[4 * kCellEmpty];
   const int lane = threadIdx.x;
   const int total = src.plan ? src.plan->gtiles : src.single_gtiles;
   int32_t* slow = src.plan ? src.plan->slow : src.slow;
@@ -590,100 +638,57 @@ __global__ __launch_bounds__(kLanes) void k_global_stream(FrameSource src, KPara
     f = uniform_frame(f);
     const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
-    global_stream_tile<TH, false>(f, kp, t, fidx, gt, tr * TH, (gt - tr * f.gcols) * kGlobalTW, lane, slow, cap);
+    global_stream_tile<TH, false>(f, kp, t, fidx, gt, tr * TH, (gt - tr * f.gcols) * kGlobalTW, lane, slow, cap,
+                                  s_cells);
   }
 }
 
-// Phase 2, queued quarters, step 1 (Sec. III "Large Hole Fill"): every cell
-// of the quarter's output rows that is empty after stage 5 takes the largest
-// stage-5 value of the full (2 rl + 1)^2 window around it (cells outside the
-// image ignored).  One wave per quarter; for each empty cell the wave's lanes
-// split the window (two lanes per window row, up to 16 columns each) and
-// reduce.  The values go to f.v6p at the cell; nothing else is written, so
-// the stage-5 reads of other waves are unaffected.
+// Phase 2, queued cells, step 1 (Sec. III "Large Hole Fill"): a cell empty
+// after stage 5 takes the largest stage-5 value of the full (2 rl + 1)^2
+// window around it (cells outside the image ignored).  One wave per cell:
+// lane l covers window column (l mod 32) - rl and, for l < 32, the window
+// rows -rl .. -rl + 15, else the next 16, so every load instruction reads
+// two short row segments; a wave-wide max reduces the lanes.  The value
+// goes to f.v6p at the cell only, so the stage-5 reads of other waves are
+// unaffected.
 constexpr int kFillRad = 15;   // largest large-fill radius (31x31)
 
-template <int TH>
-__global__ __launch_bounds__(kLanes) void k_fill_pixels(FrameSource src, KParams kp) {
-  constexpr int QR = TH / 4;
-  __shared__ int s_top[kGlobalTW + 2 * kFillRad];   // column tops of the window columns
+__global__ __launch_bounds__(kLanes) void k_fill_cells(FrameSource src, KParams kp) {
   const int lane = threadIdx.x;
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
-  const int count = slow[0];
+  const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
+  const int count = min(slow[3], 4 * kCellEmpty * cap);
+  const int32_t* cells = slow + cell_queue_offset(cap);
   const int rl = kp.rl;
-  const int kthr = key(kp.thr);
-  // window share of this lane: row y + dy, columns x + c_lo .. x + c_hi
-  const int dy = (lane >> 1) - rl;
-  const bool lrow = (lane >> 1) < 2 * rl + 1;
-  const int c_lo = -rl + 16 * (lane & 1), c_hi = min(rl, c_lo + 15);
-  const int32_t* queue = slow + sparse_queue_offset(0);
+  const int dx = (lane & 31) - rl;
+  const bool colw = (lane & 31) <= 2 * rl;
+  const int dy0 = 16 * (lane >> 5) - rl;
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
-    const int fidx = queue[2 * i], tq = queue[2 * i + 1];
-    const int gt = tq & ((1 << 27) - 1), qk = (unsigned)tq >> 27;
+    const int fidx = cells[2 * i], pos = cells[2 * i + 1];
     FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
     f = uniform_frame(f);
     const int H = f.H, W = f.W;
-    const int tr = gt / f.gcols;
-    const int y0 = tr * TH + qk * QR, tx0 = (gt - tr * f.gcols) * kGlobalTW;
+    const int y = uni(pos / W), x = uni(pos - (pos / W) * W);
     gcint* v4 = gc(f.v4);
-    gcint* top = gc(f.top);
-    gint* v6p = gw(f.v6p);
-    __syncthreads();                                   // s_top of the previous quarter is no longer read
-    for (int c = lane; c < kGlobalTW + 2 * rl; c += kLanes) {
-      const int gx = tx0 - rl + c;
-      s_top[c] = (gx >= 0 && gx < W) ? top[gx] : H;    // >= H: no extension
-    }
-    __syncthreads();
-    // stage-5 value at (gy, gx), both clamped into the image and to the
-    // window columns: rows above the column's top take the top value.  The
-    // loads are unconditional (the callers mask the values), so that a
-    // batch of them is in flight at once.
-    const int wmax = kGlobalTW + 2 * rl - 1;
-    auto v5 = [&](int gy, int gx) -> int {
-      const int idx = clampi_s(gx - (tx0 - rl), 0, wmax);
-      const int x = clampi_s(tx0 - rl + idx, 0, W - 1);
-      const int y = clampi_s(gy, 0, H - 1);
-      const int tt = s_top[idx];
-      return v4[(size_t)(tt < H ? max(y, tt) : y) * W + x];
-    };
-    const int ca = tx0 + 2 * lane, cb = ca + 1;        // lanes 0..59 hold the 120 output columns
-    const bool ina = lane < 60 && ca < W, inb = lane < 60 && cb < W;
-    int va[QR], vb[QR];
+    const int gx = x + dx;
+    const bool colin = colw && gx >= 0 && gx < W;
+    const int xc = clampi_s(gx, 0, W - 1);
+    const int tt = kp.extrapolate ? gc(f.top)[xc] : H;   // stage 5: rows above the top read the top
+    int w[16];
 #pragma unroll
-    for (int r = 0; r < QR; ++r) {
-      va[r] = v5(y0 + r, ca);
-      vb[r] = v5(y0 + r, cb);
+    for (int k = 0; k < 16; ++k) {
+      const int yc = clampi_s(y + dy0 + k, 0, H - 1);
+      w[k] = v4[(size_t)(tt < H ? max(yc, tt) : yc) * W + xc];
+    }
+    int m = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int gy = y + dy0 + k;
+      m = max(m, (colin && dy0 + k <= rl && gy >= 0 && gy < H) ? w[k] : 0);
     }
 #pragma unroll
-    for (int r = 0; r < QR; ++r) {
-      const bool rin = y0 + r < H;
-      va[r] = (ina && rin) ? va[r] : kInfKey;
-      vb[r] = (inb && rin) ? vb[r] : kInfKey;
-    }
-#pragma unroll
-    for (int r = 0; r < QR; ++r) {
-      const int y = y0 + r;
-      unsigned long long ma = __ballot(va[r] <= kthr), mb = __ballot(vb[r] <= kthr);
-      while ((ma | mb) != 0) {
-        int x;
-        if (ma != 0) { const int l = __ffsll((long long)ma) - 1; ma &= ma - 1; x = tx0 + 2 * l; }
-        else { const int l = __ffsll((long long)mb) - 1; mb &= mb - 1; x = tx0 + 2 * l + 1; }
-        const int gy = y + dy;
-        const bool rok = lrow && gy >= 0 && gy < H;
-        int w[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) w[c] = v5(gy, x + c_lo + c);
-        int m = 0;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const int gx = x + c_lo + c;
-          m = max(m, (rok && c_lo + c <= c_hi && gx >= 0 && gx < W) ? w[c] : 0);
-        }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
-        if (lane == 0) v6p[(size_t)y * W + x] = m;
-      }
-    }
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if (lane == 0) gw(f.v6p)[(size_t)pos] = m;
   }
 }
 
@@ -719,7 +724,7 @@ __global__ __launch_bounds__(kLanes) void k_fill_dense(FrameSource src, KParams 
   const int lane = threadIdx.x;
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
-  const int count = slow[2];
+  const int count = min(slow[2], 4 * cap);
   const int32_t* queue = slow + dense_queue_offset(cap);
   const int rl = kp.rl;
   const int kthr = key(kp.thr);
@@ -803,7 +808,7 @@ __global__ __launch_bounds__(kLanes) void k_global_patched(FrameSource src, KPar
   const int lane = threadIdx.x;
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
-  const int n_sparse = slow[0], count = n_sparse + slow[2];
+  const int n_sparse = min(slow[0], 4 * cap), count = n_sparse + min(slow[2], 4 * cap);
   if (kp.last_stage == 5) return;                   // the stage-5 map needs no second pass
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int32_t* e = i < n_sparse ? slow + sparse_queue_offset(cap) + 2 * i
@@ -814,7 +819,7 @@ __global__ __launch_bounds__(kLanes) void k_global_patched(FrameSource src, KPar
     f = uniform_frame(f);
     const int tr = gt / f.gcols;
     global_stream_tile<QR, true>(f, kp, 0, fidx, gt, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane,
-                                 nullptr, 0);
+                                 nullptr, 0, nullptr);
   }
 }
 
@@ -867,18 +872,17 @@ hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int t
   return hipGetLastError();
 }
 
-hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
-  // the fill values of the queued quarters (per cell, then separably for the
-  // dense ones), then the second pass over both queues
-  if (tile_id == 5) hipLaunchKernelGGL((k_fill_pixels<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else if (tile_id == 6) hipLaunchKernelGGL((k_fill_pixels<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else if (tile_id == 7) hipLaunchKernelGGL((k_fill_pixels<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else return hipErrorInvalidValue;
+hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, int cell_grid,
+                                hipStream_t s) {
+  // the fill values of the queued cells and of the dense quarters, then the
+  // second pass over both quarter queues
+  hipLaunchKernelGGL(k_fill_cells, dim3(cell_grid), dim3(kLanes), 0, s, src, kp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (tile_id == 5) hipLaunchKernelGGL((k_fill_dense<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else if (tile_id == 6) hipLaunchKernelGGL((k_fill_dense<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else hipLaunchKernelGGL((k_fill_dense<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 7) hipLaunchKernelGGL((k_fill_dense<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else return hipErrorInvalidValue;
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (tile_id == 5) hipLaunchKernelGGL((k_global_patched<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);

@@ -57,7 +57,10 @@ def test_argument_checks_return_before_any_gpu_call():
     assert _ws_call(p, out=0) == L.IPB_ERR_INVALID_ARG
     assert _ws_call(p, H=0) == L.IPB_ERR_INVALID_ARG
     assert _ws_call(p, W=-3) == L.IPB_ERR_INVALID_ARG
-    assert _ws_call(p, H=1 << 16, W=1 << 15) == L.IPB_ERR_INVALID_ARG        # H * W >= 2^31
+    assert _ws_call(p, H=1 << 16, W=1 << 15) == L.IPB_ERR_INVALID_ARG        # H * W = 2^31
+    assert _ws_call(p, H=(1 << 15) + 1, W=1 << 15) == L.IPB_ERR_INVALID_ARG  # H * W > 2^30
+    assert L.lib().ipb_workspace_bytes(1 << 15, 1 << 15, ctypes.byref(p)) > 0   # H * W = 2^30 is accepted
+    assert L.lib().ipb_workspace_bytes((1 << 15) + 1, 1 << 15, ctypes.byref(p)) == 0
     assert _ws_call(p, stage=0) == L.IPB_ERR_INVALID_ARG
     assert _ws_call(p, stage=10) == L.IPB_ERR_INVALID_ARG
     assert _ws_call(p, ws=0) == L.IPB_ERR_WORKSPACE
