@@ -182,13 +182,18 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
     xb_ = ldf(row, lb);
   };
 #pragma unroll
-  for (int u = 0; u < 8; ++u) fetch(u, da[u], db[u]);
+  for (int u = 0; u < 8; ++u) {
+    fetch(u, da[u], db[u]);
+    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch in row order
+  }
 
+  // Whole blocks of 8 rows: the steps past row n compute values no row
+  // stores (their rows are past the tile), which keeps the unrolled block
+  // free of exits.
   for (int rb = 0; rb < n; rb += 8) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int r = rb + u;
-      if (r >= n) break;
       const int q = q0 + r;
 
       // Stage 1: inversion of input row q.
@@ -271,8 +276,8 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       }
       const int o4 = q - D4;
       const bool o4row = o4 >= ty0 && o4 < ty0 + TH && o4 < H;
-      int oa = 0, ob = 0;
-      if (last >= 4 && o4row) {
+      int oa, ob;
+      {
         const int ma = max3i(max3i(hf[(u - 6) & 7][0], hf[(u - 5) & 7][0], hf[(u - 4) & 7][0]),
                              max3i(hf[(u - 3) & 7][0], hf[(u - 2) & 7][0], hf[(u - 1) & 7][0]), hf[u][0]);
         const int mb = max3i(max3i(hf[(u - 6) & 7][1], hf[(u - 5) & 7][1], hf[(u - 4) & 7][1]),
@@ -280,8 +285,8 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         const int c3a = v3[(u - 3) & 7][0], c3b = v3[(u - 3) & 7][1];
         oa = c3a <= kthr ? ma : c3a;
         ob = c3b <= kthr ? mb : c3b;
-        if (outa && oa > kthr && first_a == kNoTop) first_a = o4;
-        if (outb && ob > kthr && first_b == kNoTop) first_b = o4;
+        first_a = (o4row && outa && oa > kthr && first_a == kNoTop) ? o4 : first_a;
+        first_b = (o4row && outb && ob > kthr && first_b == kNoTop) ? o4 : first_b;
       }
 
       // One store site per row, for the map of the last stage asked for
@@ -304,7 +309,7 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
 }
 
 template <int SHAPE, int RD, int TH>
-__global__ __launch_bounds__(kLanes) void k_local_stream(FrameSource src, KParams kp) {
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(5))) void k_local_stream(FrameSource src, KParams kp) {
   const int lane = threadIdx.x;
   const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
   for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
