@@ -21,6 +21,9 @@
 // about the edge pixel (reflect-101).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "common.hpp"
 #include "networks.hpp"
 
@@ -128,6 +131,17 @@ __host__ __device__ constexpr int se_half_s(int dy) {
   int e = 0;
   while (e < R && 4 * ((e + 1) * (e + 1) + ady * ady) <= (2 * R + 1) * (2 * R + 1)) ++e;
   return e;
+}
+
+// f(integral_constant<int, 0>) .. f(integral_constant<int, 7>): the ring
+// slots of one block of 8 rows as compile-time constants.
+template <class F, int... Us>
+__device__ __forceinline__ void for_slots_impl(F&& f, std::integer_sequence<int, Us...>) {
+  (f(std::integral_constant<int, Us>{}), ...);
+}
+template <class F>
+__device__ __forceinline__ void for_slots(F&& f) {
+  for_slots_impl(f, std::make_integer_sequence<int, 8>{});
 }
 
 // ---------------------------------------------------------------------------
@@ -358,9 +372,9 @@ __device__ __forceinline__ double hsum5(double wc, double w1, double w2, int m2,
 // true, one quarter): cells empty after stage 5 read their stage-6 value
 // from f.v6p (written by k_fill_cells / k_fill_dense).  s_cells: LDS lists
 // of the first kCellEmpty empty cells of each quarter (first pass only).
-template <int TH, bool PATCHED>
-__device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int fidx, int gt, int ty0, int tx0,
-                                   int lane, int32_t* slow, int cap, int* s_cells) {
+template <int TH, bool PATCHED, bool FAST>
+__device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int fidx, int gt,
+                                                   int ty0, int tx0, int lane, int32_t* slow, int cap, int* s_cells) {
   const int H = f.H, W = f.W;
   const float thr = kp.thr, off = kp.off;
   const int kthr = key(thr);
@@ -452,180 +466,214 @@ __device__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t,
 #pragma unroll
   for (int u = 0; u < 8; ++u) fetch(u, u);
 
-  for (int rb = 0; rb < n; rb += 8) {
+  // One row step: row q = q0 + r enters, the median of row q - 2 and the
+  // outputs of row q - 4 leave.  FAST: the default chain (5x5 median, 5x5
+  // Gaussian, every stage); rows outside the frame are the replicated
+  // border rows the loads already give (the median's border rule), so only
+  // the Gaussian's reflected rows and the output rows need checks.
+  auto step = [&](auto u_tag, const int r, auto warm_tag) __attribute__((always_inline)) {
+    constexpr int u = decltype(u_tag)::value;            // ring slot: a constant
+    constexpr bool WARM = decltype(warm_tag)::value;     // the first block: r = u
+    const int q = q0 + r;
+    int va = detach(pa[u]), vb = detach(pb[u]);
+    if (PATCHED) {
+      va = va <= kthr ? detach(ppa[u]) : va;
+      vb = vb <= kthr ? detach(ppb[u]) : vb;
+    }
+    fetch(r + 8, u);
+    if (FAST || (q >= 0 && q < H)) {
+      if (!PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
+        // row q is an input row of quarter k when k*QR - 4 <= q - ty0 < (k+1)*QR + 4
+        const int rel = q - ty0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int r = rb + u;
-      if (r >= n) break;
-      const int q = q0 + r;
-      int va = detach(pa[u]), vb = detach(pb[u]);
-      if (PATCHED) {
-        va = va <= kthr ? detach(ppa[u]) : va;
-        vb = vb <= kthr ? detach(ppb[u]) : vb;
-      }
-      fetch(r + 8, u);
-      if (q >= 0 && q < H) {
-        if (!PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
-          // row q is an input row of quarter k when k*QR - 4 <= q - ty0 < (k+1)*QR + 4
-          const int rel = q - ty0;
+        for (int k = 0; k < 4; ++k)
+          if (rel >= k * (TH / 4) - 4 && rel < (k + 1) * (TH / 4) + 4) qmask |= 1u << k;
+        if (rel >= 0 && rel < TH && q < H) {
+          // empty output cells of this row: count them per quarter and
+          // list the first kCellEmpty of each quarter (y * W + x)
+          const bool ea = outa && va <= kthr, eb = outb && vb <= kthr;
+          const unsigned long long ma = __ballot(ea), mb = __ballot(eb);
+          const unsigned long long below = (1ull << lane) - 1ull;
+          const int k = rel / (TH / 4);
+          int base = 0;
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (rel >= k * (TH / 4) - 4 && rel < (k + 1) * (TH / 4) + 4) qmask |= 1u << k;
-          if (rel >= 0 && rel < TH) {
-            // empty output cells of this row: count them per quarter and
-            // list the first kCellEmpty of each quarter (y * W + x)
-            const bool ea = outa && va <= kthr, eb = outb && vb <= kthr;
-            const unsigned long long ma = __ballot(ea), mb = __ballot(eb);
-            const unsigned long long below = (1ull << lane) - 1ull;
-            const int k = rel / (TH / 4);
-            int base = 0;
+          for (int kk = 0; kk < 4; ++kk)
+            if (kk == k) base = qempty[kk];
+          const int ja = base + __popcll(ma & below), jb = base + __popcll(ma) + __popcll(mb & below);
+          if (ea && ja < kCellEmpty) s_cells[k * kCellEmpty + ja] = q * W + ca;
+          if (eb && jb < kCellEmpty) s_cells[k * kCellEmpty + jb] = q * W + cb;
+          const int n_e = __popcll(ma) + __popcll(mb);
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-              if (kk == k) base = qempty[kk];
-            const int ja = base + __popcll(ma & below), jb = base + __popcll(ma) + __popcll(mb & below);
-            if (ea && ja < kCellEmpty) s_cells[k * kCellEmpty + ja] = q * W + ca;
-            if (eb && jb < kCellEmpty) s_cells[k * kCellEmpty + jb] = q * W + cb;
-            const int n_e = __popcll(ma) + __popcll(mb);
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-              if (kk == k) qempty[kk] += n_e;
-          }
-        }
-        if ((last == 5 || last == 6) && q >= ty0 && q < ty0 + TH) {
-          gint* o = out + (size_t)q * W;
-          if (outa) stk(o, ua, va);
-          if (outb) stk(o, ub, vb);
+          for (int kk = 0; kk < 4; ++kk)
+            if (kk == k) qempty[kk] += n_e;
         }
       }
-      if (median) {
-        window_update(Sa, raw[(u - 5) & 7][0], va);
-        window_update(Sb, raw[(u - 5) & 7][1], vb);
-      }
-      raw[u][0] = va;
-      raw[u][1] = vb;
-      if (r < 4) continue;
-
-      // Stage 7: median of row m = q - 2.
-      const int m = q - 2;
-      int v7a, v7b;
-      if (median) {
-        int Lb[5], La[5], Rb[5], m1[10], m2[10], core[6];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          Lb[k] = from_prev(Sb[k]);   // column a - 1
-          La[k] = from_prev(Sa[k]);   // column a - 2
-          Rb[k] = from_next(Sb[k]);   // column b + 2
-        }
-        net::merge5_5(Lb, Sa, m1);    // columns a - 1, a
-#pragma unroll
-        for (int k = 0; k < 10; ++k) m2[k] = from_next(m1[k]);   // columns b, b + 1
-        net::ranks7_12_of_10_10(m1, m2, core);
-        net::rank5_of_6_5(core, La, &v7a);
-        net::rank5_of_6_5(core, Rb, &v7b);
-      } else {
-        v7a = raw[(u - 2) & 7][0];
-        v7b = raw[(u - 2) & 7][1];
-      }
-      if (edge_cols) {   // out-of-image columns take the median of their reflect-101 column
-        const int fa0 = __shfl(v7a, sla), fa1 = __shfl(v7b, sla);
-        const int fb0 = __shfl(v7a, slb), fb1 = __shfl(v7b, slb);
-        if (!ina) v7a = sela ? fa1 : fa0;
-        if (!inb) v7b = selb ? fb1 : fb0;
-      }
-      s7[u][0] = v7a;
-      s7[u][1] = v7b;
-      if (last == 7 && m >= ty0 && m < ty0 + TH && m < H && m >= 0) {
-        gint* o = out + (size_t)m * W;
-        if (outa) stk(o, ua, v7a);
-        if (outb) stk(o, ub, v7b);
-      }
-
-      // Stage 8: horizontal sums of row m (reflect-101 rows are copies).
-      if (m >= 0) {
-        if (m < H) {
-          const int La = from_prev(v7a), Lb = from_prev(v7b), Ra = from_next(v7a), Rb = from_next(v7b);
-          hs[u][0] = hsum5(wc, w1, w2, La, Lb, v7a, v7b, Ra);
-          hs[u][1] = hsum5(wc, w1, w2, Lb, v7a, v7b, Ra, Rb);
-          if (m == 2 && q0 + 2 <= 0) {            // rows -1, -2 mirror rows 1, 2
-            hs[(u - 3) & 7][0] = hs[(u - 1) & 7][0];
-            hs[(u - 3) & 7][1] = hs[(u - 1) & 7][1];
-            hs[(u - 4) & 7][0] = hs[u][0];
-            hs[(u - 4) & 7][1] = hs[u][1];
-          }
-        } else if (m == H) {                      // row H mirrors H - 2
-          hs[u][0] = hs[(u - 2) & 7][0];
-          hs[u][1] = hs[(u - 2) & 7][1];
-        } else if (m == H + 1) {                  // row H + 1 mirrors H - 3
-          hs[u][0] = hs[(u - 4) & 7][0];
-          hs[u][1] = hs[(u - 4) & 7][1];
-        }
-      }
-      if (r < 8) continue;
-
-      // Stages 8 and 9 for row g = q - 4.
-      const int g = q - 4;
-      if (g >= ty0 && g < ty0 + TH && g < H && last >= 8) {
-        const int ca7 = s7[(u - 2) & 7][0], cb7 = s7[(u - 2) & 7][1];
-        const bool ma = ca7 > kthr, mb = cb7 > kthr;
-        float oa, ob;
-        if (kp.rg > 0) {
-          const double ga = fma(wc, hs[(u - 2) & 7][0],
-                                fma(w1, hs[(u - 3) & 7][0] + hs[(u - 1) & 7][0],
-                                    w2 * (hs[(u - 4) & 7][0] + hs[u][0])));
-          const double gb = fma(wc, hs[(u - 2) & 7][1],
-                                fma(w1, hs[(u - 3) & 7][1] + hs[(u - 1) & 7][1],
-                                    w2 * (hs[(u - 4) & 7][1] + hs[u][1])));
-          oa = ma ? (float)(ga * gsc) : 0.f;
-          ob = mb ? (float)(gb * gsc) : 0.f;
-        } else {
-          oa = ma ? val(ca7) : 0.f;
-          ob = mb ? val(cb7) : 0.f;
-        }
-        if (last == 9) {
-          oa = ma ? off - oa : 0.f;
-          ob = mb ? off - ob : 0.f;
-        }
-        gint* o = out + (size_t)g * W;
-        if (outa) stk(o, ua, key(oa));
-        if (outb) stk(o, ub, key(ob));
+      if (!FAST && (last == 5 || last == 6) && q >= ty0 && q < ty0 + TH) {
+        const unsigned ro = (unsigned)q * W4;
+        if (outa) stk(out, ro + ua, va);
+        if (outb) stk(out, ro + ub, vb);
       }
     }
-  }
+    if (FAST || median) {
+      window_update(Sa, raw[(u - 5) & 7][0], va);
+      window_update(Sb, raw[(u - 5) & 7][1], vb);
+    }
+    raw[u][0] = va;
+    raw[u][1] = vb;
+    if (WARM && u < 4) return;
+
+    // Stage 7: median of row m = q - 2.
+    const int m = q - 2;
+    int v7a, v7b;
+    if (FAST || median) {
+      int Lb[5], La[5], Rb[5], m1[10], m2[10], core[6];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        Lb[k] = from_prev(Sb[k]);   // column a - 1
+        La[k] = from_prev(Sa[k]);   // column a - 2
+        Rb[k] = from_next(Sb[k]);   // column b + 2
+      }
+      net::merge5_5(Lb, Sa, m1);    // columns a - 1, a
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m2[k] = from_next(m1[k]);   // columns b, b + 1
+      net::ranks7_12_of_10_10(m1, m2, core);
+      net::rank5_of_6_5(core, La, &v7a);
+      net::rank5_of_6_5(core, Rb, &v7b);
+    } else {
+      v7a = raw[(u - 2) & 7][0];
+      v7b = raw[(u - 2) & 7][1];
+    }
+    if (edge_cols) {   // out-of-image columns take the median of their reflect-101 column
+      const int fa0 = __shfl(v7a, sla), fa1 = __shfl(v7b, sla);
+      const int fb0 = __shfl(v7a, slb), fb1 = __shfl(v7b, slb);
+      if (!ina) v7a = sela ? fa1 : fa0;
+      if (!inb) v7b = selb ? fb1 : fb0;
+    }
+    s7[u][0] = v7a;
+    s7[u][1] = v7b;
+    if (!FAST && last == 7 && m >= ty0 && m < ty0 + TH && m < H && m >= 0) {
+      const unsigned ro = (unsigned)m * W4;
+      if (outa) stk(out, ro + ua, v7a);
+      if (outb) stk(out, ro + ub, v7b);
+    }
+
+    // Stage 8: horizontal sums of row m (reflect-101 rows are copies).
+    if (FAST || (m >= 0 && m < H)) {
+      const int La = from_prev(v7a), Lb = from_prev(v7b), Ra = from_next(v7a), Rb = from_next(v7b);
+      hs[u][0] = hsum5(wc, w1, w2, La, Lb, v7a, v7b, Ra);
+      hs[u][1] = hsum5(wc, w1, w2, Lb, v7a, v7b, Ra, Rb);
+    }
+    if (m == 2 && q0 + 2 <= 0) {                // rows -1, -2 mirror rows 1, 2
+      hs[(u - 3) & 7][0] = hs[(u - 1) & 7][0];
+      hs[(u - 3) & 7][1] = hs[(u - 1) & 7][1];
+      hs[(u - 4) & 7][0] = hs[u][0];
+      hs[(u - 4) & 7][1] = hs[u][1];
+    } else if (m == H) {                        // row H mirrors H - 2
+      hs[u][0] = hs[(u - 2) & 7][0];
+      hs[u][1] = hs[(u - 2) & 7][1];
+    } else if (m == H + 1) {                    // row H + 1 mirrors H - 3
+      hs[u][0] = hs[(u - 4) & 7][0];
+      hs[u][1] = hs[(u - 4) & 7][1];
+    }
+    if (WARM) return;
+
+    // Stages 8 and 9 for row g = q - 4.
+    const int g = q - 4;
+    if (FAST ? g < H : (g >= ty0 && g < ty0 + TH && g < H && last >= 8)) {
+      const int ca7 = s7[(u - 2) & 7][0], cb7 = s7[(u - 2) & 7][1];
+      const bool ma = ca7 > kthr, mb = cb7 > kthr;
+      float oa, ob;
+      if (FAST || kp.rg > 0) {
+        const double ga = fma(wc, hs[(u - 2) & 7][0],
+                              fma(w1, hs[(u - 3) & 7][0] + hs[(u - 1) & 7][0],
+                                  w2 * (hs[(u - 4) & 7][0] + hs[u][0])));
+        const double gb = fma(wc, hs[(u - 2) & 7][1],
+                              fma(w1, hs[(u - 3) & 7][1] + hs[(u - 1) & 7][1],
+                                  w2 * (hs[(u - 4) & 7][1] + hs[u][1])));
+        oa = ma ? (float)(ga * gsc) : 0.f;
+        ob = mb ? (float)(gb * gsc) : 0.f;
+      } else {
+        oa = ma ? val(ca7) : 0.f;
+        ob = mb ? val(cb7) : 0.f;
+      }
+      if (FAST || last == 9) {
+        oa = ma ? off - oa : 0.f;
+        ob = mb ? off - ob : 0.f;
+      }
+      const unsigned ro = (unsigned)g * W4;
+      if (outa) stk(out, ro + ua, key(oa));
+      if (outb) stk(out, ro + ub, key(ob));
+    }
+  };
+
+  // The first block fills the windows (rows q0 .. q0 + 7); n is a multiple
+  // of 8, so every later block is whole.
+  static_assert(TH % 8 == 0, "tile rows");
+  auto block = [&](const int rb, auto warm_tag) __attribute__((always_inline)) {
+    for_slots([&](auto u_tag) __attribute__((always_inline)) { step(u_tag, rb + decltype(u_tag)::value, warm_tag); });
+  };
+  block(0, std::true_type{});
+  for (int rb = 8; rb < n; rb += 8) block(rb, std::false_type{});
   // Quarters whose median and blur inputs still hold an empty pixel need the
   // 31x31 fill and a second pass: queue them (tile id in the low 27 bits,
   // quarter above), and queue the empty cells of those with few of them.
   if (!PATCHED && kp.extrapolate && qmask != 0) {
     __syncthreads();                                 // the cell lists are complete
-    int32_t* cells = slow + cell_queue_offset(cap);
+    // One atomic per queue and tile: thousands of tiles push at once on
+    // frames with large holes, and atomics on one address serialise.
+    unsigned dmask = 0, smask = 0;
+    int ncell = 0;
+#pragma unroll
     for (int qk = 0; qk < 4; ++qk) {
       if (((qmask >> qk) & 1u) == 0) continue;
+      if (qempty[qk] > kCellEmpty) {
+        dmask |= 1u << qk;
+      } else {
+        smask |= 1u << qk;
+        ncell += qempty[qk];
+      }
+    }
+    int ps = 0, pd = 0, pc = 0;
+    if (lane == 0) {
+      if (smask) ps = atomicAdd(slow + 0, __popc(smask));
+      if (dmask) pd = atomicAdd(slow + 2, __popc(dmask));
+      if (ncell) pc = atomicAdd(slow + 3, ncell);
+    }
+    ps = __shfl(ps, 0);
+    pd = __shfl(pd, 0);
+    pc = __shfl(pc, 0);
+    // (the bounds hold when every tile is visited once after a reset; a
+    // repeated launch without one drops entries instead of overrunning)
+    if (lane < 4 && ((qmask >> lane) & 1u)) {
+      const unsigned below = (1u << lane) - 1u;
+      const bool dense = (dmask >> lane) & 1u;
+      const int pos = dense ? pd + __popc(dmask & below) : ps + __popc(smask & below);
+      if (pos < 4 * cap) {
+        int32_t* e = slow + (dense ? dense_queue_offset(cap) : sparse_queue_offset(cap)) + 2 * pos;
+        e[0] = fidx;
+        e[1] = gt | (lane << 27);
+      }
+    }
+    int32_t* cells = slow + cell_queue_offset(cap);
+#pragma unroll
+    for (int qk = 0; qk < 4; ++qk) {
+      if (((smask >> qk) & 1u) == 0) continue;
       const int ne = qempty[qk];
-      const bool dense = ne > kCellEmpty;
-      // (the bounds hold when every tile is visited once after a reset; a
-      // repeated launch without one drops entries instead of overrunning)
-      if (lane == 0) {
-        const int pos = atomicAdd(slow + (dense ? 2 : 0), 1);
-        if (pos < 4 * cap) {
-          int32_t* e = slow + (dense ? dense_queue_offset(cap) : sparse_queue_offset(cap)) + 2 * pos;
-          e[0] = fidx;
-          e[1] = gt | (qk << 27);
-        }
+      if (lane < ne && pc + lane < 4 * kCellEmpty * cap) {
+        cells[2 * (pc + lane)] = fidx;
+        cells[2 * (pc + lane) + 1] = s_cells[qk * kCellEmpty + lane];
       }
-      if (!dense && ne > 0) {
-        int pos = 0;
-        if (lane == 0) pos = atomicAdd(slow + 3, ne);
-        pos = __shfl(pos, 0);
-        if (lane < ne && pos + lane < 4 * kCellEmpty * cap) {
-          cells[2 * (pos + lane)] = fidx;
-          cells[2 * (pos + lane) + 1] = s_cells[qk * kCellEmpty + lane];
-        }
-      }
+      pc += ne;
     }
   }
 }
 
-template <int TH>
-__global__ __launch_bounds__(kLanes) void k_global_stream(FrameSource src, KParams kp) {
+// The default chain (5x5 median, 5x5 Gaussian, every stage) takes the
+// kernels' FAST variant.
+inline bool fast_chain(const KParams& kp) { return kp.rm == 2 && kp.rg == 2 && kp.last_stage == 9; }
+
+template <int TH, bool FAST>
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) void k_global_stream(FrameSource src, KParams kp) {
   __shared__ int s_cells[4 * kCellEmpty];
   const int lane = threadIdx.x;
   const int total = src.plan ? src.plan->gtiles : src.single_gtiles;
@@ -643,8 +691,8 @@ __global__ __launch_bounds__(kLanes) void k_global_stream(FrameSource src, KPara
     f = uniform_frame(f);
     const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
-    global_stream_tile<TH, false>(f, kp, t, fidx, gt, tr * TH, (gt - tr * f.gcols) * kGlobalTW, lane, slow, cap,
-                                  s_cells);
+    global_stream_tile<TH, false, FAST>(f, kp, t, fidx, gt, tr * TH, (gt - tr * f.gcols) * kGlobalTW, lane, slow,
+                                        cap, s_cells);
   }
 }
 
@@ -715,18 +763,22 @@ __device__ __forceinline__ void vhgw31(const int* a, int* out) {
 }
 
 // Phase 2, queued quarters with many empty cells, step 1: the same fill
-// values, computed separably for the whole quarter.  The stage-5 values of
-// the quarter's rows +- rl and columns +- rl go to LDS, their horizontal
-// window maxima (van Herk/Gil-Werman for the 31-wide window) to a second LDS
-// array, and each empty cell takes the vertical max of those.
+// values, computed separably for the whole quarter by a workgroup of four
+// waves.  The stage-5 values of the quarter's rows +- rl and columns +- rl
+// go to LDS; their horizontal window maxima (van Herk/Gil-Werman for the
+// 31-wide window) replace them in place; each empty cell takes the
+// vertical max of those (for the 31-row window: the rows all the quarter's
+// windows share, then the prefix and suffix maxima at both ends).
 constexpr int kDW = kGlobalTW + 2 * kFillRad + 8;    // 158 staged columns (4 runs of 32 outputs + 30)
+constexpr int kDenseThreads = 256;
 
 template <int TH>
-__global__ __launch_bounds__(kLanes) void k_fill_dense(FrameSource src, KParams kp) {
+__global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, KParams kp) {
   constexpr int QR = TH / 4, SR = QR + 2 * kFillRad;
+  static_assert(SR <= kDenseThreads / 4, "one row of 128 horizontal maxima per four threads");
   __shared__ int S[SR * kDW];
-  __shared__ int Hm[SR * 128];
-  const int lane = threadIdx.x;
+  __shared__ int s_top[kDW];
+  const int tid = threadIdx.x;
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int count = min(slow[2], 4 * cap);
@@ -742,63 +794,96 @@ __global__ __launch_bounds__(kLanes) void k_fill_dense(FrameSource src, KParams 
     const int tr = gt / f.gcols;
     const int y0 = tr * TH + qk * QR, tx0 = (gt - tr * f.gcols) * kGlobalTW;
     gcint* v4 = gc(f.v4);
-    gcint* top = gc(f.top);
     gint* v6p = gw(f.v6p);
     const int sr = QR + 2 * rl;
     __syncthreads();                                    // LDS of the previous quarter is no longer read
-    // stage-5 values: window column cc = lane + 64 j, rows y0 - rl ..
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int cc = lane + 64 * j;
-      if (cc < kDW) {
-        const int gx = tx0 - rl + cc;
-        const bool colin = gx >= 0 && gx < W;
-        const int x = clampi_s(gx, 0, W - 1);
-        const int tt = kp.extrapolate ? top[x] : H;
+    if (tid < kDW) {                                    // column tops of the staged columns (>= H: none)
+      const int x = clampi_s(tx0 - rl + tid, 0, W - 1);
+      s_top[tid] = kp.extrapolate ? gc(f.top)[x] : H;
+    }
+    __syncthreads();
+    // stage-5 values; cells outside the image are 0, which no max selects
+    // over a non-empty value
 #pragma unroll 8
-        for (int rr = 0; rr < sr; ++rr) {
-          const int gy = y0 - rl + rr;
-          const int y = clampi_s(gy, 0, H - 1);
-          const int v = v4[(size_t)(tt < H ? max(y, tt) : y) * W + x];
-          S[rr * kDW + cc] = (colin && gy >= 0 && gy < H) ? v : 0;
+    for (int idx = tid; idx < sr * kDW; idx += kDenseThreads) {
+      const int rr = idx / kDW, cc = idx - rr * kDW;
+      const int gx = tx0 - rl + cc, gy = y0 - rl + rr;
+      const int x = clampi_s(gx, 0, W - 1), y = clampi_s(gy, 0, H - 1);
+      const int tt = s_top[cc];
+      const int v = v4[(size_t)(tt < H ? max(y, tt) : y) * W + x];
+      S[idx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? v : 0;
+    }
+    __syncthreads();
+    // horizontal window maxima of the 128 (>= 120) quarter columns, written
+    // over the staged values once every row has been read
+    {
+      const int rr = tid >> 2, j0 = (tid & 3) * 32;
+      const bool act = rr < sr;
+      int o[32];
+      if (act) {
+        if (rl == kFillRad) {
+          int a[62];
+#pragma unroll
+          for (int c = 0; c < 62; ++c) a[c] = S[rr * kDW + j0 + c];
+          vhgw31(a, o);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 32; ++c) {
+            const int* p = S + rr * kDW + j0 + c;
+            int m = p[0];
+            for (int d = 1; d <= 2 * rl; ++d) m = max(m, p[d]);
+            o[c] = m;
+          }
         }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) S[rr * kDW + j0 + c] = o[c];
       }
     }
     __syncthreads();
-    // horizontal window maxima of the 128 (>= 120) quarter columns
-    for (int w = lane; w < sr * 4; w += kLanes) {
-      const int rr = w >> 2, j0 = (w & 3) * 32;
-      if (rl == kFillRad) {
-        int a[62], o[32];
+    // vertical max at the empty cells of the quarter's own rows, one column
+    // per thread.  Output row r takes rows r .. r + 2 rl; when 2 rl >= QR - 2
+    // they split into rows r .. QR - 2 (a suffix maximum), QR - 1 .. 2 rl
+    // (shared by every row) and 2 rl + 1 .. 2 rl + r (a prefix maximum).
+    for (int c = tid; c < kGlobalTW; c += kDenseThreads) {
+      const int gx = tx0 + c;
+      if (gx >= W) continue;
+      const int tt = s_top[c + rl];
+      if (2 * rl >= QR - 2) {
+        int mid = 0;
+        for (int d = QR - 1; d <= 2 * rl; ++d) mid = max(mid, S[d * kDW + c]);
+        int lo[QR], hi[QR];
+        int acc = 0;
+        lo[QR - 1] = 0;
 #pragma unroll
-        for (int c = 0; c < 62; ++c) a[c] = S[rr * kDW + j0 + c];
-        vhgw31(a, o);
+        for (int r = QR - 2; r >= 0; --r) {
+          acc = max(acc, S[r * kDW + c]);
+          lo[r] = acc;
+        }
+        acc = 0;
+        hi[0] = 0;
 #pragma unroll
-        for (int c = 0; c < 32; ++c) Hm[rr * 128 + j0 + c] = o[c];
+        for (int r = 1; r < QR; ++r) {
+          acc = max(acc, S[(2 * rl + r) * kDW + c]);
+          hi[r] = acc;
+        }
+#pragma unroll
+        for (int r = 0; r < QR; ++r) {
+          const int gy = y0 + r;
+          if (gy >= H) break;
+          const int v = v4[(size_t)(tt < H ? max(gy, tt) : gy) * W + gx];
+          if (v <= kthr) v6p[(size_t)gy * W + gx] = max(max(mid, lo[r]), hi[r]);
+        }
       } else {
-        for (int c = 0; c < 32; ++c) {
-          const int* p = S + rr * kDW + j0 + c;
-          int m = p[0];
-          for (int d = 1; d <= 2 * rl; ++d) m = max(m, p[d]);
-          Hm[rr * 128 + j0 + c] = m;
-        }
-      }
-    }
-    __syncthreads();
-    // vertical max at the empty cells of the quarter's own rows
-    const int ca = 2 * lane;                            // lanes 0..59: quarter columns ca, ca + 1
-    if (lane < 60) {
-      for (int r = 0; r < QR && y0 + r < H; ++r) {
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-          const int c = ca + s2, gx = tx0 + c;
-          if (gx >= W) continue;
-          const int v = S[(r + rl) * kDW + c + rl];
+        for (int r = 0; r < QR && y0 + r < H; ++r) {
+          const int gy = y0 + r;
+          const int v = v4[(size_t)(tt < H ? max(gy, tt) : gy) * W + gx];
           if (v > kthr) continue;
-          int m = v;
-          const int* p = Hm + r * 128 + c;
-          for (int d = 0; d <= 2 * rl; ++d) m = max(m, p[d * 128]);
-          v6p[(size_t)(y0 + r) * W + gx] = m;
+          int m = 0;
+          for (int d = 0; d <= 2 * rl; ++d) m = max(m, S[(r + d) * kDW + c]);
+          v6p[(size_t)gy * W + gx] = m;
         }
       }
     }
@@ -807,8 +892,8 @@ __global__ __launch_bounds__(kLanes) void k_fill_dense(FrameSource src, KParams 
 
 // Phase 2, queued quarters, step 2: median, blur and output inversion of
 // the quarter again, with the stage-6 values of step 1.
-template <int TH>
-__global__ __launch_bounds__(kLanes) void k_global_patched(FrameSource src, KParams kp) {
+template <int TH, bool FAST>
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) void k_global_patched(FrameSource src, KParams kp) {
   constexpr int QR = TH / 4;
   const int lane = threadIdx.x;
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
@@ -823,8 +908,8 @@ __global__ __launch_bounds__(kLanes) void k_global_patched(FrameSource src, KPar
     FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
     f = uniform_frame(f);
     const int tr = gt / f.gcols;
-    global_stream_tile<QR, true>(f, kp, 0, fidx, gt, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane,
-                                 nullptr, 0, nullptr);
+    global_stream_tile<QR, true, FAST>(f, kp, 0, fidx, gt, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane,
+                                       nullptr, 0, nullptr);
   }
 }
 
@@ -870,10 +955,15 @@ hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int ti
 }
 
 hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
-  if (tile_id == 5) hipLaunchKernelGGL((k_global_stream<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else if (tile_id == 6) hipLaunchKernelGGL((k_global_stream<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else if (tile_id == 7) hipLaunchKernelGGL((k_global_stream<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  const bool fast = fast_chain(kp);
+#define IPB_GS(TH)                                                                                     \
+  if (fast) hipLaunchKernelGGL((k_global_stream<TH, true>), dim3(grid), dim3(kLanes), 0, s, src, kp); \
+  else hipLaunchKernelGGL((k_global_stream<TH, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  if (tile_id == 5) { IPB_GS(64) }
+  else if (tile_id == 6) { IPB_GS(32) }
+  else if (tile_id == 7) { IPB_GS(128) }
   else return hipErrorInvalidValue;
+#undef IPB_GS
   return hipGetLastError();
 }
 
@@ -884,15 +974,21 @@ hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int t
   hipLaunchKernelGGL(k_fill_cells, dim3(cell_grid), dim3(kLanes), 0, s, src, kp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (tile_id == 5) hipLaunchKernelGGL((k_fill_dense<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else if (tile_id == 6) hipLaunchKernelGGL((k_fill_dense<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else if (tile_id == 7) hipLaunchKernelGGL((k_fill_dense<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  const int dgrid = std::max(1, grid / 4);   // four waves per workgroup
+  if (tile_id == 5) hipLaunchKernelGGL((k_fill_dense<64>), dim3(dgrid), dim3(kDenseThreads), 0, s, src, kp);
+  else if (tile_id == 6) hipLaunchKernelGGL((k_fill_dense<32>), dim3(dgrid), dim3(kDenseThreads), 0, s, src, kp);
+  else if (tile_id == 7) hipLaunchKernelGGL((k_fill_dense<128>), dim3(dgrid), dim3(kDenseThreads), 0, s, src, kp);
   else return hipErrorInvalidValue;
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (tile_id == 5) hipLaunchKernelGGL((k_global_patched<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else if (tile_id == 6) hipLaunchKernelGGL((k_global_patched<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else hipLaunchKernelGGL((k_global_patched<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  const bool fast = fast_chain(kp);
+#define IPB_GP(TH)                                                                                      \
+  if (fast) hipLaunchKernelGGL((k_global_patched<TH, true>), dim3(grid), dim3(kLanes), 0, s, src, kp); \
+  else hipLaunchKernelGGL((k_global_patched<TH, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  if (tile_id == 5) { IPB_GP(64) }
+  else if (tile_id == 6) { IPB_GP(32) }
+  else { IPB_GP(128) }
+#undef IPB_GP
   return hipGetLastError();
 }
 
@@ -904,9 +1000,10 @@ int stream_resident_blocks(int phase, int tile_id, const KParams& kp) {
 #undef X
     return 1;
   }
-  if (tile_id == 5) return occupancy_s(k_global_stream<64>);
-  if (tile_id == 6) return occupancy_s(k_global_stream<32>);
-  if (tile_id == 7) return occupancy_s(k_global_stream<128>);
+  const bool fast = fast_chain(kp);
+  if (tile_id == 5) return fast ? occupancy_s(k_global_stream<64, true>) : occupancy_s(k_global_stream<64, false>);
+  if (tile_id == 6) return fast ? occupancy_s(k_global_stream<32, true>) : occupancy_s(k_global_stream<32, false>);
+  if (tile_id == 7) return fast ? occupancy_s(k_global_stream<128, true>) : occupancy_s(k_global_stream<128, false>);
   return 1;
 }
 
