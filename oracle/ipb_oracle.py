@@ -38,7 +38,14 @@ design notes):
   * the Gaussian uses reflect-101 borders; sigma <= 0 means binomial taps
     (1 4 6 4 1)/16 for size 5; it is computed over the whole map and written
     only where the median output is non-empty (mask taken before the blur);
-  * the output inversion is masked by that same mask; empties stay +0.0.
+  * the output inversion is masked by that same mask; empties stay +0.0;
+  * the bilateral blur (the alternative of Sec. IV, Table 3) weighs each
+    tap by exp(-(dy^2 + dx^2) / (2 s_space^2)) exp(-(v_q - v_p)^2 /
+    (2 s_color^2)), divides by the sum of the weights, uses reflect-101
+    borders and the Gaussian's mask; the paper gives no sigmas, so they are
+    parameters (defaults 2 px and 1.5 in depth units);
+  * a limited extension (the point-cloud advice of Sec. IV) copies the top
+    value into at most extend_rows rows above it (0: no limit).
 
 Parity pins: brute force on tiny maps, SciPy's ndimage routines, closed
 forms and invariants (tests/test_oracle_*.py).  Parity unpinned: the readings
@@ -56,6 +63,7 @@ F32 = np.float32
 F64 = np.float64
 
 SE_FULL, SE_CROSS, SE_DIAMOND, SE_CIRCLE = 0, 1, 2, 3
+BLUR_GAUSSIAN, BLUR_BILATERAL = 0, 1
 
 
 @dataclasses.dataclass
@@ -72,6 +80,10 @@ class Params:
     gauss_sigma: float = 0.0         # <= 0: binomial taps
     max_depth: float = 100.0         # the inversion offset, "Depth Inversion"
     valid_thresh: float = 0.1        # empty iff value <= this
+    blur: int = BLUR_GAUSSIAN        # step 8: Gaussian or bilateral (Sec. IV, Table 3)
+    bilateral_sigma_space: float = 2.0
+    bilateral_sigma_color: float = 1.5
+    extend_rows: int = 0             # rows the extension reaches above the top; 0 = all (Sec. IV)
 
 
 # ---------------------------------------------------------------- kernels --
@@ -167,14 +179,16 @@ def step4_small_fill(v: np.ndarray, p: Params) -> np.ndarray:
 
 def step5_extend(v: np.ndarray, p: Params) -> np.ndarray:
     """Extension to top of frame (Sec. III): in each column, the topmost
-    non-empty value is copied into all rows above it."""
+    non-empty value is copied into all rows above it (into at most
+    extend_rows of them when that is positive, Sec. IV)."""
     thr = F32(p.valid_thresh)
     out = v.copy()
     for x in range(v.shape[1]):
         rows = np.flatnonzero(v[:, x] > thr)
         if rows.size:
             top = rows[0]
-            out[:top, x] = v[top, x]
+            first = max(0, top - p.extend_rows) if p.extend_rows > 0 else 0
+            out[first:top, x] = v[top, x]
     return out
 
 
@@ -233,13 +247,38 @@ def gaussian_sum(v: np.ndarray, size: int, sigma: float) -> np.ndarray:
     return g
 
 
+def bilateral_sum(v: np.ndarray, size: int, sigma_space: float, sigma_color: float) -> np.ndarray:
+    """Bilateral blur (Sec. IV, Table 3), float64 before rounding: the
+    weighted mean of the window, each tap weighted by its distance and by
+    its value's difference from the centre value."""
+    H, W = v.shape
+    r = size // 2
+    ss = F64(F32(sigma_space))
+    sc = F64(F32(sigma_color))
+    c = v.astype(F64)
+    pad = c[np.ix_(reflect101(np.arange(-r, H + r), H), reflect101(np.arange(-r, W + r), W))]
+    num = np.zeros((H, W), F64)
+    den = np.zeros((H, W), F64)
+    for i in range(size):
+        for j in range(size):
+            dy, dx = i - r, j - r
+            q = pad[i:i + H, j:j + W]
+            w = math.exp(-(dy * dy + dx * dx) / (2.0 * ss * ss)) * np.exp(-((q - c) ** 2) / (2.0 * sc * sc))
+            num += w * q
+            den += w
+    return num / den
+
+
 def step8_gaussian(v7: np.ndarray, p: Params) -> np.ndarray:
-    """Gaussian blur (Sec. III), written where the median output is
-    non-empty."""
+    """Gaussian blur (Sec. III), or the bilateral blur (Sec. IV), written
+    where the median output is non-empty."""
     mask = v7 > F32(p.valid_thresh)
     if p.gauss_size == 0:
         return np.where(mask, v7, F32(0.0)).astype(F32)
-    g = gaussian_sum(v7, p.gauss_size, p.gauss_sigma).astype(F32)
+    if p.blur == BLUR_BILATERAL:
+        g = bilateral_sum(v7, p.gauss_size, p.bilateral_sigma_space, p.bilateral_sigma_color).astype(F32)
+    else:
+        g = gaussian_sum(v7, p.gauss_size, p.gauss_sigma).astype(F32)
     return np.where(mask, g, F32(0.0)).astype(F32)
 
 

@@ -83,7 +83,9 @@ def fill(v, size, thr):
             for y in range(len(v))]
 
 
-def extend(v, thr):
+def extend(v, thr, limit=0):
+    """Copy each column's topmost non-empty value upward (at most `limit`
+    rows when limit > 0)."""
     H, W = len(v), len(v[0])
     out = [row[:] for row in v]
     for x in range(W):
@@ -94,7 +96,28 @@ def extend(v, thr):
                 break
         if top is not None:
             for y in range(top):
-                out[y][x] = v[top][x]
+                if limit <= 0 or top - y <= limit:
+                    out[y][x] = v[top][x]
+    return out
+
+
+def bilateral(v, size, sigma_space, sigma_color):
+    """Bilateral weighted mean per pixel, float64, reflect-101 borders."""
+    H, W = len(v), len(v[0])
+    r = size // 2
+    out = [[0.0] * W for _ in range(H)]
+    for y in range(H):
+        for x in range(W):
+            c = v[y][x]
+            num = den = 0.0
+            for dy in range(-r, r + 1):
+                for dx in range(-r, r + 1):
+                    q = v[refl(y + dy, H)][refl(x + dx, W)]
+                    w = math.exp(-(dy * dy + dx * dx) / (2.0 * sigma_space ** 2)) * \
+                        math.exp(-((q - c) ** 2) / (2.0 * sigma_color ** 2))
+                    num += w * q
+                    den += w
+            out[y][x] = num / den
     return out
 
 

@@ -401,3 +401,117 @@ def test_pins_catch_planted_mistakes(monkeypatch):
         return w / 16.0
     assert _pins_fail(monkeypatch, "gaussian_taps", bad_taps,
                       [test_golden_gauss, lambda: test_gauss_matches_scipy(0.0)]) >= 1
+
+
+# --------------------------------------------- bilateral blur, limited extension --
+# (the blur alternative of Table 3 and the point-cloud advice of Sec. IV)
+
+def _random_v7(rng, H, W, dens=0.7):
+    v = np.zeros((H, W), F32)
+    keep = rng.random((H, W)) < dens
+    v[keep] = rng.uniform(20.0, 99.0, int(keep.sum())).astype(F32)
+    return v
+
+
+@pytest.mark.parametrize("size,ss,sc", [(5, 2.0, 1.5), (3, 1.0, 0.5), (5, 0.7, 10.0)])
+def test_bilateral_matches_brute_force(size, ss, sc):
+    rng = np.random.default_rng(size * 100 + int(ss * 10))
+    for H, W in [(1, 1), (2, 3), (6, 7), (9, 5)]:
+        v = _random_v7(rng, H, W)
+        got = O.bilateral_sum(v, size, ss, sc)
+        want = np.array(brute.bilateral(brute.to_lists(v), size, float(F32(ss)), float(F32(sc))))
+        assert np.allclose(got, want, rtol=1e-12, atol=0.0), (H, W)
+
+
+def test_bilateral_closed_forms():
+    # a constant map is unchanged (the weights are normalised)
+    c = np.full((7, 9), 37.25, F32)
+    assert np.allclose(O.bilateral_sum(c, 5, 2.0, 1.5), 37.25, rtol=1e-15)
+    # with a huge colour sigma only the spatial weights remain: the
+    # normalised sampled Gaussian of the same sigma
+    rng = np.random.default_rng(3)
+    v = _random_v7(rng, 11, 13)
+    wide = O.bilateral_sum(v, 5, 1.3, 1e7)
+    gauss = O.gaussian_sum(v, 5, 1.3)
+    assert np.allclose(wide, gauss, rtol=1e-9)
+    # with a tiny colour sigma, taps of another value weigh nothing: on a
+    # two-valued map every pixel keeps its own value
+    two = np.where(rng.random((8, 10)) < 0.5, F32(30.0), F32(60.0)).astype(F32)
+    assert np.allclose(O.bilateral_sum(two, 5, 2.0, 0.01), two.astype(np.float64), rtol=1e-14, atol=0.0)
+    # an edge far larger than the colour sigma stays sharp
+    edge = np.zeros((6, 12), F32)
+    edge[:, :6], edge[:, 6:] = 20.0, 50.0
+    out = O.bilateral_sum(edge, 5, 2.0, 1.5)
+    assert np.allclose(out[:, :6], 20.0, atol=1e-6) and np.allclose(out[:, 6:], 50.0, atol=1e-6)
+
+
+def test_bilateral_stage_masks_like_the_gaussian():
+    rng = np.random.default_rng(4)
+    v7 = _random_v7(rng, 9, 9, dens=0.5)
+    p = O.Params(blur=O.BLUR_BILATERAL)
+    v8 = O.step8_gaussian(v7, p)
+    assert np.array_equal(v8 > 0, v7 > F32(0.1))
+    b = O.bilateral_sum(v7, 5, 2.0, 1.5).astype(F32)
+    assert same_bits(v8[v7 > F32(0.1)], b[v7 > F32(0.1)])
+
+
+@pytest.mark.parametrize("limit", [0, 1, 2, 5, 100])
+def test_limited_extension_matches_brute_force(limit):
+    rng = np.random.default_rng(limit + 7)
+    for H, W in [(1, 4), (6, 5), (12, 9)]:
+        v = np.zeros((H, W), F32)
+        for x in range(W):
+            if rng.random() < 0.8:
+                t = int(rng.integers(0, H))
+                v[t:, x] = np.where(rng.random(H - t) < 0.6, rng.uniform(1, 90, H - t), 0).astype(F32)
+                v[t, x] = F32(rng.uniform(1, 90))
+        got = O.step5_extend(v, O.Params(extend_rows=limit))
+        want = np.array(brute.extend(brute.to_lists(v), float(F32(0.1)), limit), F32)
+        assert same_bits(got, want), (limit, H, W)
+
+
+def test_limited_extension_bounds():
+    rng = np.random.default_rng(8)
+    v = np.zeros((20, 6), F32)
+    v[10:, :] = rng.uniform(5, 50, (10, 6)).astype(F32)
+    full = O.step5_extend(v, O.Params())
+    assert same_bits(O.step5_extend(v, O.Params(extend_rows=20)), full)
+    one = O.step5_extend(v, O.Params(extend_rows=1))
+    assert same_bits(one[9], v[10]) and not one[:9].any()
+    three = O.step5_extend(v, O.Params(extend_rows=3))
+    assert same_bits(three[7:10], np.repeat(v[10:11], 3, axis=0)) and not three[:7].any()
+
+
+def test_bilateral_and_limit_pins_catch_planted_mistakes(monkeypatch):
+    # the weights left unnormalised: the constant-map pin fails
+    def bad_bilateral(v, size, ss, sc):
+        H, W = v.shape
+        r = size // 2
+        c = v.astype(np.float64)
+        pad = c[np.ix_(O.reflect101(np.arange(-r, H + r), H), O.reflect101(np.arange(-r, W + r), W))]
+        num = np.zeros((H, W))
+        for i in range(size):
+            for j in range(size):
+                q = pad[i:i + H, j:j + W]
+                num += math.exp(-((i - r) ** 2 + (j - r) ** 2) / (2 * ss * ss)) * \
+                    np.exp(-((q - c) ** 2) / (2 * sc * sc)) * q
+        return num
+    assert _pins_fail(monkeypatch, "bilateral_sum", bad_bilateral, [test_bilateral_closed_forms]) >= 1
+
+    # the range term dropped (a plain Gaussian): the two-valued pin fails
+    def no_range(v, size, ss, sc):
+        return O.gaussian_sum(v, size, ss)
+    assert _pins_fail(monkeypatch, "bilateral_sum", no_range, [test_bilateral_closed_forms]) >= 1
+
+    # the limit off by one row
+    def bad_limit(v, p):
+        out = v.copy()
+        for x in range(v.shape[1]):
+            rows = np.flatnonzero(v[:, x] > F32(p.valid_thresh))
+            if rows.size:
+                top = rows[0]
+                first = max(0, top - p.extend_rows - 1) if p.extend_rows > 0 else 0
+                out[first:top, x] = v[top, x]
+        return out
+    assert _pins_fail(monkeypatch, "step5_extend", bad_limit,
+                      [test_limited_extension_bounds, lambda: test_limited_extension_matches_brute_force(2)]) >= 1
