@@ -59,6 +59,17 @@ typedef enum {
  * |dx| + |dy| <= k/2, CIRCLE dx^2 + dy^2 <= (k/2)^2. */
 typedef enum { IPB_SE_FULL = 0, IPB_SE_CROSS = 1, IPB_SE_DIAMOND = 2, IPB_SE_CIRCLE = 3 } ipb_se;
 
+/* Stage-8 blur: the Gaussian of the final design, or the bilateral blur the
+ * paper compares it with (Sec. IV "Noise Reduction through Blurring",
+ * Table 3) and recommends for point clouds.  The bilateral blur weighs each
+ * tap of the (gauss_size)^2 window by exp(-(dy^2 + dx^2) / (2 s^2)) *
+ * exp(-(v_q - v_p)^2 / (2 c^2)) (s = bilateral_sigma_space in pixels,
+ * c = bilateral_sigma_color in depth units), divides by the weights' sum,
+ * reflects about the edge pixel at the border and, like the Gaussian, is
+ * written only where the median output is non-empty.  It is computed in
+ * float32 (within 1e-5 relative of the float64 definition). */
+typedef enum { IPB_BLUR_GAUSSIAN = 0, IPB_BLUR_BILATERAL = 1 } ipb_blur;
+
 /* Pipeline parameters.  Defaults (ipb_params_default) are the paper's final
  * design.  Supported values are listed per field; anything else returns
  * IPB_ERR_UNSUPPORTED. */
@@ -80,6 +91,12 @@ typedef struct {
   float valid_thresh;       /* a value is empty iff <= this; 0.1; > 0              */
   int32_t tile_local;       /* tile shape id for stages 1-4; 0 = automatic         */
   int32_t tile_global;      /* tile shape id for stages 5-9; 0 = automatic         */
+  int32_t blur;             /* ipb_blur; GAUSSIAN                                  */
+  float bilateral_sigma_space;  /* > 0; 2.0 (not given in the paper)              */
+  float bilateral_sigma_color;  /* > 0; 1.5 (not given in the paper)              */
+  int32_t extend_rows;      /* >= 0; rows above its top a column's value reaches in
+                               stage 5; 0 = up to row 0 (Sec. III); a positive
+                               limit is the point-cloud advice of Sec. IV         */
 } ipb_params;
 
 /* Fill *p with the paper's defaults (Sec. III; Tables 2 and 3: diamond 5x5

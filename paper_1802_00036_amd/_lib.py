@@ -35,6 +35,10 @@ class CParams(ctypes.Structure):
         ("valid_thresh", ctypes.c_float),
         ("tile_local", ctypes.c_int32),
         ("tile_global", ctypes.c_int32),
+        ("blur", ctypes.c_int32),
+        ("bilateral_sigma_space", ctypes.c_float),
+        ("bilateral_sigma_color", ctypes.c_float),
+        ("extend_rows", ctypes.c_int32),
     ]
 
 

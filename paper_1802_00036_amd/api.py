@@ -15,6 +15,7 @@ import torch
 from . import _lib as L
 
 SE_FULL, SE_CROSS, SE_DIAMOND, SE_CIRCLE = 0, 1, 2, 3
+BLUR_GAUSSIAN, BLUR_BILATERAL = 0, 1
 N_STAGES = 9
 
 
@@ -35,6 +36,10 @@ class Params:
     valid_thresh: float = 0.1
     tile_local: int = 0
     tile_global: int = 0
+    blur: int = BLUR_GAUSSIAN            # stage 8: Gaussian, or bilateral (Sec. IV, Table 3)
+    bilateral_sigma_space: float = 2.0
+    bilateral_sigma_color: float = 1.5
+    extend_rows: int = 0                 # stage-5 reach above a column's top; 0 = to row 0
 
     def to_c(self) -> L.CParams:
         c = L.CParams()

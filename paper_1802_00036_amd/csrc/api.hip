@@ -62,6 +62,11 @@ int resolve(const ipb_params* p, Resolved* r) {
   if (p->gauss_size != 0 && !odd_in(p->gauss_size, 3, 5)) return IPB_ERR_UNSUPPORTED;
   if (p->tile_local < 0 || p->tile_local > kTileIds) return IPB_ERR_INVALID_ARG;
   if (p->tile_global < 0 || p->tile_global > kTileIds) return IPB_ERR_INVALID_ARG;
+  if (p->blur != IPB_BLUR_GAUSSIAN && p->blur != IPB_BLUR_BILATERAL) return IPB_ERR_INVALID_ARG;
+  if (!std::isfinite(p->bilateral_sigma_space) || !(p->bilateral_sigma_space > 0.f) ||
+      !std::isfinite(p->bilateral_sigma_color) || !(p->bilateral_sigma_color > 0.f))
+    return IPB_ERR_INVALID_ARG;
+  if (p->extend_rows < 0) return IPB_ERR_INVALID_ARG;
 
   KParams& k = r->kp;
   std::memset(&k, 0, sizeof(k));
@@ -76,6 +81,15 @@ int resolve(const ipb_params* p, Resolved* r) {
   k.off = p->max_depth;
   k.thr = p->valid_thresh;
   k.last_stage = 9;
+  k.blur = p->blur;
+  k.ext_rows = p->extend_rows;
+  {
+    const double ss = p->bilateral_sigma_space, sc = p->bilateral_sigma_color;
+    k.bl_kc = static_cast<float>(1.0 / (2.0 * sc * sc));
+    for (int dy = 0; dy < 3; ++dy)
+      for (int dx = 0; dx < 3; ++dx)
+        k.bl_ws[dy * 3 + dx] = static_cast<float>(std::exp(-(double)(dy * dy + dx * dx) / (2.0 * ss * ss)));
+  }
   if (k.rg > 0) {
     if (p->gauss_sigma <= 0.f) {
       // binomial taps, kept as integers; the sum is scaled once at the end
@@ -96,7 +110,7 @@ int resolve(const ipb_params* p, Resolved* r) {
   if (need_local > 12) return IPB_ERR_UNSUPPORTED;
   if (k.rl + k.rm + k.rg > 19) return IPB_ERR_UNSUPPORTED;
   const bool ls_ok = stream_local_supported(k.shape, k.rd, k.rc, k.rf);
-  const bool gs_ok = stream_global_supported(k.rm, k.rg);
+  const bool gs_ok = stream_global_supported(k.rm, k.rg) && !(k.blur == IPB_BLUR_BILATERAL && k.rg > 0);
   r->ltile = p->tile_local ? p->tile_local : (ls_ok ? 5 : 1);
   r->gtile = p->tile_global ? p->tile_global : (gs_ok ? 6 : 1);
   r->lstream = r->ltile >= 5;
@@ -400,6 +414,10 @@ void ipb_params_default(ipb_params* p) {
   p->valid_thresh = 0.1f;
   p->tile_local = 0;
   p->tile_global = 0;
+  p->blur = IPB_BLUR_GAUSSIAN;
+  p->bilateral_sigma_space = 2.f;
+  p->bilateral_sigma_color = 1.5f;
+  p->extend_rows = 0;
 }
 
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p) {

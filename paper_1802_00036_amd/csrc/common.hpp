@@ -65,7 +65,18 @@ struct KParams {
   int32_t pad;
   double gw[3];       // Gaussian taps: centre, +-1, +-2 (integers for the binomial case)
   double gscale;      // applied to the 2-D sum (1/256 for binomial 5, 1/16 for 3)
+  int32_t blur;       // 0 Gaussian, 1 bilateral
+  int32_t ext_rows;   // stage-5 reach above the top; 0 = unlimited
+  float bl_kc;        // bilateral: 1 / (2 sigma_color^2)
+  float bl_ws[9];     // bilateral spatial weights, [|dy| * 3 + |dx|]
 };
+
+// Row of the stage-4 map that stage 5 reads for row y of a column whose
+// topmost non-empty row is top (top >= H: none): the top row above it,
+// within ext_rows rows when that is positive.
+__host__ __device__ inline int v5_row(int y, int top, int H, int ext_rows) {
+  return (top < H && y < top && (ext_rows <= 0 || y >= top - ext_rows)) ? top : y;
+}
 
 // Where a launch finds its frames: a device plan, or one frame by value.
 struct FrameSource {

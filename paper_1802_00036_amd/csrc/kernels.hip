@@ -402,6 +402,42 @@ __device__ void reflect_fixup(float* B, int bpitch, int bcol0, int r0, int r1, i
 
 // Stages 8 and 9: Gaussian (fp64 sum, reflect-101 border already in B),
 // masked by the median output, then the output inversion.
+// Stages 8 (bilateral variant, Sec. IV, Table 3) and 9: the weighted mean
+// of the (2 RG + 1)^2 window of the median map, each tap weighted by its
+// distance and by the difference of its value from the centre value
+// (float32 throughout), masked like the Gaussian.  B holds the median map
+// with its reflect-101 border cells already filled.
+template <int RG>
+__device__ void bilat_out(const float* B, int bpitch, int bcol0, int r0, int r1, int c0, int c1,
+                          int oy, int ox, int H, int W, const KParams& kp, float* dst, bool stage8,
+                          int ylim, int xlim) {
+  const int rb = min(r1, min(ylim, H) - oy), cb = min(c1, min(xlim, W) - ox);
+  const float thr = kp.thr, off = kp.off, kc = kp.bl_kc;
+  for_column_runs(r0, rb, c0, cb, [&](int c, int ya, int yb) {
+    const int gx = ox + c;
+    for (int y = ya; y < yb; ++y) {
+      const float* p = B + y * bpitch + (c - bcol0);
+      const float v7 = p[0];
+      float num = 0.f, den = 0.f;
+#pragma unroll
+      for (int dy = -RG; dy <= RG; ++dy) {
+#pragma unroll
+        for (int dx = -RG; dx <= RG; ++dx) {
+          const float q = p[dy * bpitch + dx];
+          const float d = q - v7;
+          const float w = kp.bl_ws[(dy < 0 ? -dy : dy) * 3 + (dx < 0 ? -dx : dx)] * expf(-(d * d) * kc);
+          num += w * q;
+          den += w;
+        }
+      }
+      const bool m = v7 > thr;
+      const float v8 = m ? num / den : 0.f;
+      const float o = m ? off - v8 : 0.f;
+      dst[(size_t)(oy + y) * W + gx] = stage8 ? v8 : o;
+    }
+  });
+}
+
 template <int RG>
 __device__ void gauss_out(const float* B, int bpitch, int bcol0, int r0, int r1, int c0, int c1,
                           int oy, int ox, int H, int W, const KParams& kp, float* dst, bool stage8,
@@ -482,10 +518,11 @@ __device__ void global_tile(const FrameDesc& f, const KParams& kp, int ty0, int 
   // Stage 5 (extension to top of frame) while loading the cells the median
   // and blur need; note whether any of them is still empty.
   const int n0 = kHG - E, n1 = kHG + TH + E;
+  const int ext = kp.ext_rows;
   auto load5 = [&](int r, int c) -> float {
     const int gy = oy + r, gx = ox + c;
     if (gy < 0 || gy >= H || gx < 0 || gx >= W) return 0.f;
-    return gy < s_top[c] ? s_topv[c] : f.v4[(size_t)gy * W + gx];
+    return (gy < s_top[c] && (ext <= 0 || gy >= s_top[c] - ext)) ? s_topv[c] : f.v4[(size_t)gy * W + gx];
   };
   const int m0 = kHG - E, m1 = kHG + TW + E;   // needed columns
   int empty = 0;
@@ -542,7 +579,9 @@ __device__ void global_tile(const FrameDesc& f, const KParams& kp, int ty0, int 
 
   // Stages 8 and 9.
   const bool st8 = kp.last_stage == 8;
-  if (kp.rg == 2) gauss_out<2>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
+  if (kp.blur == 1 && kp.rg == 2) bilat_out<2>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
+  else if (kp.blur == 1 && kp.rg == 1) bilat_out<1>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
+  else if (kp.rg == 2) gauss_out<2>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
   else if (kp.rg == 1) gauss_out<1>(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
   else plain_out(B, BW, B0, kHG, kHG + TH, kHG, kHG + TW, oy, ox, H, W, kp, f.out, st8, ylim, xlim);
 }

@@ -403,13 +403,19 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
   // offsets, the larger of the row's and the top cell's (0 without a top).
   // Every load is issued unconditionally, so that the compiler waits for
   // each row alone instead of draining the prefetch.
+  // With a limited reach (ext_rows > 0) only rows at or below top - ext_rows
+  // copy the top cell: byte offsets from tlim up.
   const unsigned W4 = 4u * (unsigned)W;
-  unsigned toffa = 0, toffb = 0;
+  unsigned toffa = 0, toffb = 0, tlima = 0, tlimb = 0;
   if (kp.extrapolate) {
     gcint* top = gc(f.top);
     const int t_a = top[xa], t_b = top[xb];
     if (t_a < H) toffa = (unsigned)t_a * W4 + oxa;
     if (t_b < H) toffb = (unsigned)t_b * W4 + oxb;
+    if (kp.ext_rows > 0) {
+      if (t_a < H) tlima = (unsigned)max(t_a - kp.ext_rows, 0) * W4 + oxa;
+      if (t_b < H) tlimb = (unsigned)max(t_b - kp.ext_rows, 0) * W4 + oxb;
+    }
   }
 
   // reflect-101 source lane/slot of this lane's columns, for the Gaussian's border
@@ -456,8 +462,16 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
   gcint* v6p = gc(f.v6p);
   auto fetch = [&](int r, int u_) {
     const unsigned rowoff = (unsigned)clampi_s(q0 + r, 0, H - 1) * W4;
-    pa[u_] = ldk(v4, max(rowoff + oxa, toffa));
-    pb[u_] = ldk(v4, max(rowoff + oxb, toffb));
+    unsigned oa_ = rowoff + oxa, ob_ = rowoff + oxb;
+    if constexpr (FAST) {
+      oa_ = max(oa_, toffa);
+      ob_ = max(ob_, toffb);
+    } else {
+      oa_ = (oa_ < toffa && oa_ >= tlima) ? toffa : oa_;
+      ob_ = (ob_ < toffb && ob_ >= tlimb) ? toffb : ob_;
+    }
+    pa[u_] = ldk(v4, oa_);
+    pb[u_] = ldk(v4, ob_);
     if (PATCHED) {
       ppa[u_] = ldk(v6p, rowoff + oxa);
       ppb[u_] = ldk(v6p, rowoff + oxb);
@@ -670,7 +684,9 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
 
 // The default chain (5x5 median, 5x5 Gaussian, every stage) takes the
 // kernels' FAST variant.
-inline bool fast_chain(const KParams& kp) { return kp.rm == 2 && kp.rg == 2 && kp.last_stage == 9; }
+inline bool fast_chain(const KParams& kp) {
+  return kp.rm == 2 && kp.rg == 2 && kp.last_stage == 9 && kp.blur == 0 && kp.ext_rows == 0;
+}
 
 template <int TH, bool FAST>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) void k_global_stream(FrameSource src, KParams kp) {
@@ -731,7 +747,7 @@ __global__ __launch_bounds__(kLanes) void k_fill_cells(FrameSource src, KParams 
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int yc = clampi_s(y + dy0 + k, 0, H - 1);
-      w[k] = v4[(size_t)(tt < H ? max(yc, tt) : yc) * W + xc];
+      w[k] = v4[(size_t)v5_row(yc, tt, H, kp.ext_rows) * W + xc];
     }
     int m = 0;
 #pragma unroll
@@ -810,7 +826,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, K
       const int gx = tx0 - rl + cc, gy = y0 - rl + rr;
       const int x = clampi_s(gx, 0, W - 1), y = clampi_s(gy, 0, H - 1);
       const int tt = s_top[cc];
-      const int v = v4[(size_t)(tt < H ? max(y, tt) : y) * W + x];
+      const int v = v4[(size_t)v5_row(y, tt, H, kp.ext_rows) * W + x];
       S[idx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? v : 0;
     }
     __syncthreads();
@@ -873,13 +889,13 @@ __global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, K
         for (int r = 0; r < QR; ++r) {
           const int gy = y0 + r;
           if (gy >= H) break;
-          const int v = v4[(size_t)(tt < H ? max(gy, tt) : gy) * W + gx];
+          const int v = v4[(size_t)v5_row(gy, tt, H, kp.ext_rows) * W + gx];
           if (v <= kthr) v6p[(size_t)gy * W + gx] = max(max(mid, lo[r]), hi[r]);
         }
       } else {
         for (int r = 0; r < QR && y0 + r < H; ++r) {
           const int gy = y0 + r;
-          const int v = v4[(size_t)(tt < H ? max(gy, tt) : gy) * W + gx];
+          const int v = v4[(size_t)v5_row(gy, tt, H, kp.ext_rows) * W + gx];
           if (v > kthr) continue;
           int m = 0;
           for (int d = 0; d <= 2 * rl; ++d) m = max(m, S[(r + d) * kDW + c]);

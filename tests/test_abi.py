@@ -39,6 +39,8 @@ def test_params_default_is_the_paper_design():
     assert (c.dilate_shape, c.dilate_size, c.close_size, c.fill_size) == (2, 5, 5, 7)
     assert (c.extrapolate, c.large_fill_size, c.median_size, c.gauss_size) == (1, 31, 5, 5)
     assert c.max_depth == 100.0 and abs(c.valid_thresh - 0.1) < 1e-7 and c.gauss_sigma == 0.0
+    assert (c.blur, c.extend_rows) == (0, 0)
+    assert (c.bilateral_sigma_space, c.bilateral_sigma_color) == (2.0, 1.5)
 
 
 def test_status_strings():
@@ -69,7 +71,9 @@ def test_argument_checks_return_before_any_gpu_call():
     assert _ws_call(p, out=FAKE + 8) == L.IPB_ERR_INVALID_ARG                # partial overlap
     assert _ws_call(p, out=FAKE, stage=3) == L.IPB_ERR_INVALID_ARG           # in place, early stage
     assert _ws_call(p, ws=FAKE + 256) == L.IPB_ERR_INVALID_ARG              # workspace over the input
-    bad = [dict(dilate_shape=7), dict(dilate_size=4), dict(dilate_size=-1), dict(median_size=2),
+    bad = [dict(blur=2), dict(bilateral_sigma_space=0.0), dict(bilateral_sigma_color=-1.0),
+           dict(bilateral_sigma_color=float("inf")), dict(extend_rows=-1),
+           dict(dilate_shape=7), dict(dilate_size=4), dict(dilate_size=-1), dict(median_size=2),
            dict(valid_thresh=0.0), dict(max_depth=float("nan")), dict(max_depth=0.1), dict(extrapolate=2),
            dict(tile_local=99), dict(tile_global=-1)]
     for kw in bad:

@@ -33,7 +33,9 @@ def oracle_params(p: api.Params) -> oracle.Params:
     return oracle.Params(dilate_shape=p.dilate_shape, dilate_size=p.dilate_size, close_size=p.close_size,
                          fill_size=p.fill_size, extrapolate=p.extrapolate, large_fill_size=p.large_fill_size,
                          median_size=p.median_size, gauss_size=p.gauss_size, gauss_sigma=p.gauss_sigma,
-                         max_depth=p.max_depth, valid_thresh=p.valid_thresh)
+                         max_depth=p.max_depth, valid_thresh=p.valid_thresh, blur=p.blur,
+                         bilateral_sigma_space=p.bilateral_sigma_space,
+                         bilateral_sigma_color=p.bilateral_sigma_color, extend_rows=p.extend_rows)
 
 
 def assert_stage_equal(got, want, tag):
@@ -109,6 +111,10 @@ VARIANTS = [
     api.Params(large_fill_size=3),
     api.Params(max_depth=140.0),
     api.Params(valid_thresh=0.5),
+    api.Params(extend_rows=1),                                     # limited extension (Sec. IV)
+    api.Params(extend_rows=12),
+    api.Params(extend_rows=40, large_fill_size=15),
+    api.Params(extend_rows=7, median_size=3, gauss_size=3),
 ]
 
 
@@ -147,6 +153,52 @@ def test_gaussian_sigma_tolerance(sigma):
     r9 = ref[8]
     ulp = np.spacing(np.abs(r9)).astype(np.float64)
     assert np.all(np.abs(out.astype(np.float64) - r9) <= 1e-5 * r8.astype(np.float64) + ulp)
+
+
+def assert_blur_tolerance(m, p, tag):
+    """Stages 1-7 bit-exact; stage 8 within 1e-5 relative with the same mask;
+    the output within 1e-5 * v8 + one ulp (the non-dyadic blurs)."""
+    ref = oracle.complete(m, oracle_params(p))
+    for k in range(1, 8):
+        assert_stage_equal(gpu_stage(m, k, p), ref[k - 1], f"{tag} stage {k}")
+    v8 = gpu_stage(m, 8, p)
+    r8 = ref[7]
+    assert np.array_equal(v8 > 0, r8 > 0), tag
+    err = np.abs(v8.astype(np.float64) - r8)
+    assert np.all(err <= 1e-5 * np.abs(r8.astype(np.float64))), (tag, float(err.max()))
+    out = gpu_stage(m, 9, p)
+    r9 = ref[8]
+    ulp = np.spacing(np.abs(r9)).astype(np.float64)
+    assert np.all(np.abs(out.astype(np.float64) - r9) <= 1e-5 * r8.astype(np.float64) + ulp), tag
+
+
+BILATERAL = [
+    api.Params(blur=api.BLUR_BILATERAL),
+    api.Params(blur=api.BLUR_BILATERAL, median_size=0),                 # bilateral alone (Table 3)
+    api.Params(blur=api.BLUR_BILATERAL, bilateral_sigma_space=1.0, bilateral_sigma_color=0.3),
+    api.Params(blur=api.BLUR_BILATERAL, gauss_size=3, bilateral_sigma_color=8.0),
+    api.Params(blur=api.BLUR_BILATERAL, extrapolate=0, extend_rows=5),   # the point-cloud settings
+    api.Params(blur=api.BLUR_BILATERAL, extend_rows=10),
+]
+
+
+@pytest.mark.parametrize("i", range(len(BILATERAL)))
+def test_bilateral_blur_tolerance(i):
+    p = BILATERAL[i]
+    f = synth.lidar_frame(140, 270, seed=[16, i], n_rows=32, density=0.05)
+    print(f"[bilateral {i}] {p}", flush=True)
+    assert_blur_tolerance(f.sparse, p, f"bilateral {i}")
+    rng = np.random.default_rng(100 + i)
+    assert_blur_tolerance(synth.random_map(rng, 23, 41, 0.1, 1.0, 79.0), p, f"bilateral {i} random")
+    assert_blur_tolerance(synth.random_map(rng, 2, 5, 0.5, 1.0, 79.0), p, f"bilateral {i} tiny")
+
+
+def test_bilateral_batch_equals_per_frame():
+    p = api.Params(blur=api.BLUR_BILATERAL)
+    frames = [torch.from_numpy(f.sparse).to(DEV) for f in synth.config_frames(3, limit=3)]
+    outs = api.complete_batch(frames, p)
+    for f, o in zip(frames, outs):
+        assert np.array_equal(bits(o.cpu().numpy()), bits(api.complete(f, p).cpu().numpy()))
 
 
 # ------------------------------------------------------------ edge cases --
