@@ -117,3 +117,20 @@ def test_served_results_equal_alone(executor):
     if executor == "graph":
         assert ex.tiers == [1, 4]
         assert {len(eng.capacity) for eng in ex.engines.values()} <= {1, 4}
+
+
+def test_quality_sweep_runs_every_design_step():
+    from paper_1802_00036_amd import quality
+    frames = [synth.lidar_frame(120, 300, seed=[24, i], n_rows=40, density=0.05) for i in range(2)]
+    rows = quality.sweep(frames, quality.design_variants(api.Params()))
+    assert len(rows) == 13
+    for r in rows:
+        assert np.isfinite(r["rmse_mm"]) and np.isfinite(r["mae_mm"]) and 0.0 <= r["coverage"] <= 1.0
+    # the scored output is the library's: the default design equals the oracle
+    f = frames[0]
+    got = api.complete(torch.from_numpy(f.sparse).to(DEV)).cpu().numpy()
+    want = oracle.complete_map(f.sparse)
+    assert np.array_equal(got.view(np.uint32), np.asarray(want, np.float32).view(np.uint32))
+    assert np.isclose(rows[-1]["rmse_mm"], quality.pooled(
+        [api.complete(torch.from_numpy(fr.sparse).to(DEV)).cpu().numpy() for fr in frames],
+        [fr.dense_gt for fr in frames])["rmse_mm"], rtol=1e-3)
