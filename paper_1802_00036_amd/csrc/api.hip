@@ -183,6 +183,10 @@ int slow_res(int dev) {
   return slot;
 }
 
+// The stage-4 map and, past its last cell, a scratch slot that the
+// streaming kernel's idle lanes store to.
+size_t v4_bytes(int H, int W) { return align_up(sizeof(float) * (size_t)H * W + kAlign); }
+
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
@@ -227,7 +231,7 @@ void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, voi
     d.in = frames[i].in;
     d.out = frames[i].out;
     d.v4 = reinterpret_cast<float*>(base + off);
-    off += align_up(sizeof(float) * (size_t)H * W);
+    off += v4_bytes(H, W);
     d.v6p = reinterpret_cast<float*>(base + off);
     off += align_up(sizeof(float) * (size_t)H * W);
     d.top = top_base + col;
@@ -261,7 +265,8 @@ size_t batch_bytes(const ipb_frame* frames, int n, const Resolved& r) {
   for (int i = 0; i < n; ++i) gtot += (size_t)cdiv(frames[i].W, r.gtw) * cdiv(frames[i].H, r.gth);
   total += align_up(sizeof(int32_t) * cols);
   total += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot));
-  for (int i = 0; i < n; ++i) total += 2 * align_up(sizeof(float) * (size_t)frames[i].H * frames[i].W);
+  for (int i = 0; i < n; ++i)
+    total += v4_bytes(frames[i].H, frames[i].W) + align_up(sizeof(float) * (size_t)frames[i].H * frames[i].W);
   return total;
 }
 
@@ -305,9 +310,10 @@ FrameSource single_source(const float* in, int H, int W, float* out, void* ws, c
   d.out = out;
   d.v4 = static_cast<float*>(ws);
   const size_t map = align_up(sizeof(float) * (size_t)H * W);
-  d.v6p = reinterpret_cast<float*>(static_cast<char*>(ws) + map);
-  d.top = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 2 * map);
-  s.slow = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 2 * map + align_up(sizeof(int32_t) * (size_t)W));
+  const size_t map4 = v4_bytes(H, W);
+  d.v6p = reinterpret_cast<float*>(static_cast<char*>(ws) + map4);
+  d.top = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + map4 + map);
+  s.slow = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + map4 + map + align_up(sizeof(int32_t) * (size_t)W));
   d.H = H;
   d.W = W;
   d.lcols = cdiv(W, r.ltw);
@@ -322,7 +328,7 @@ FrameSource single_source(const float* in, int H, int W, float* out, void* ws, c
 
 size_t frame_ws_bytes(int H, int W, const Resolved& r) {
   const size_t gtiles = (size_t)cdiv(W, r.gtw) * cdiv(H, r.gth);
-  return 2 * align_up(sizeof(float) * (size_t)H * W) + align_up(sizeof(int32_t) * (size_t)W) +
+  return v4_bytes(H, W) + align_up(sizeof(float) * (size_t)H * W) + align_up(sizeof(int32_t) * (size_t)W) +
          align_up(sizeof(int32_t) * slow_queue_ints((int)gtiles));
 }
 
@@ -368,7 +374,8 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
   }
   if ((phase == -1 || phase == 4) && r.gstream) {
     const int per = slow_subtiles(r.gth, r.gtw);
-    const int sgrid = std::max(1, std::min(max_gt * per, slow_res(dev) * cus));
+    // frames under 3 rows or columns are rare and small: one workgroup per CU
+    const int sgrid = std::max(1, std::min(max_gt * per, cus));
     e = launch_global_slow(src, kp, r.gth, r.gtw, sgrid, s);
     if (e != hipSuccess) return hip_fail(e);
   }
@@ -389,6 +396,12 @@ int run_single(const float* in, int H, int W, const ipb_params* p, float* out, i
     return IPB_ERR_WORKSPACE;
   if (overlaps(ws, frame_ws_bytes(H, W, r), in, nb) || overlaps(ws, frame_ws_bytes(H, W, r), out, nb))
     return IPB_ERR_INVALID_ARG;
+  if (last_stage <= 4 && r.lstream) {   // the stage hooks 1-4 take the LDS kernel
+    r.lstream = false;
+    r.ltile = 1;
+    r.lth = local_tile_rows(1);
+    r.ltw = local_tile_cols(1);
+  }
   FrameSource src = single_source(in, H, W, out, ws, r);
   return launch_phases(src, r, -1, last_stage, src.single_ltiles, src.single_gtiles, W, false, s);
 }

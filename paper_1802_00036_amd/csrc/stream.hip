@@ -149,6 +149,11 @@ __device__ __forceinline__ void for_slots(F&& f) {
 constexpr int kLocalHalo = 10;                         // >= RD + 2 + 2 + 3 for RD <= 3
 constexpr int kLocalTW = 2 * kLanes - 2 * kLocalHalo;  // 108
 
+// Writes the stage-4 map into f.v4 for the later stages (the stage hooks
+// 1-4 take the LDS kernel).  The per-row work keeps to few scalar
+// instructions: row checks are one unsigned compare, the column-top record
+// is a running minimum, and the stores are unconditional, the lanes with
+// nothing to store writing to a scratch slot just past the map.
 template <int SHAPE, int RD, int TH>
 __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0, int tx0, int lane) {
   const int H = f.H, W = f.W;
@@ -164,7 +169,6 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   // they are used); loads issued on every path let the compiler wait for
   // each row alone instead of draining the prefetch
   const unsigned la = 4u * (unsigned)clampi_s(ca, 0, W - 1), lb = 4u * (unsigned)clampi_s(cb, 0, W - 1);
-  const int last = kp.last_stage;
   constexpr int D2 = RD, D3A = RD + 2, D3B = RD + 4, D4 = RD + 7;  // row delays of the stage outputs
   const int q0 = ty0 - D4;
   const int n = TH + 2 * D4;
@@ -185,15 +189,18 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
     v3[s][0] = v3[s][1] = 0;
   }
   int first_a = kNoTop, first_b = kNoTop;
-  gint* dst = gw(last >= 5 ? f.v4 : f.out);
+  gint* dst = gw(f.v4);
   gcfloat* in = gcf(f.in);
+  const unsigned W4 = 4u * (unsigned)W;
+  const unsigned sink = (unsigned)H * W4;                 // scratch slot past the stage-4 map
+  const unsigned uH = (unsigned)H;
 
   // input rows are fetched 8 rows ahead of their use
   float da[8], db[8];
   auto fetch = [&](int r, float& xa_, float& xb_) {
-    gcfloat* row = in + (size_t)clampi_s(q0 + r, 0, H - 1) * W;
-    xa_ = ldf(row, la);
-    xb_ = ldf(row, lb);
+    const unsigned rowoff = (unsigned)clampi_s(q0 + r, 0, H - 1) * W4;
+    xa_ = ldf(in, rowoff + la);
+    xb_ = ldf(in, rowoff + lb);
   };
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -213,10 +220,11 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       // Stage 1: inversion of input row q.
       int va, vb;
       {
-        const bool rin = q >= 0 && q < H;
+        const bool rin = (unsigned)q < uH;
         const float x0 = detachf(da[u]), x1 = detachf(db[u]);
         const float d0 = (rin && ina) ? x0 : 0.f, d1 = (rin && inb) ? x1 : 0.f;
         fetch(r + 8, da[u], db[u]);
+        __builtin_amdgcn_sched_barrier(0);   // issue the prefetch here, eight rows ahead
         const float v0 = off - d0, v1 = off - d1;
         va = (d0 > thr && v0 > thr) ? key(v0) : 0;
         vb = (d1 > thr && v1 > thr) ? key(v1) : 0;
@@ -245,7 +253,7 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         w2a = max(w2a, h[(u - RD + dy) & 7][se_half_s<SHAPE, RD>(dy)][0]);
         w2b = max(w2b, h[(u - RD + dy) & 7][se_half_s<SHAPE, RD>(dy)][1]);
       }
-      const bool row2 = p2 >= 0 && p2 < H;
+      const bool row2 = (unsigned)p2 < uH;
       w2a = (row2 && ina) ? w2a : 0;
       w2b = (row2 && inb) ? w2b : 0;
 
@@ -259,7 +267,7 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       const int p3 = q - D3A;
       int ta = max3i(max3i(hd[(u - 4) & 7][0], hd[(u - 3) & 7][0], hd[(u - 2) & 7][0]), hd[(u - 1) & 7][0], hd[u][0]);
       int tb = max3i(max3i(hd[(u - 4) & 7][1], hd[(u - 3) & 7][1], hd[(u - 2) & 7][1]), hd[(u - 1) & 7][1], hd[u][1]);
-      const bool row3 = p3 >= 0 && p3 < H;
+      const bool row3 = (unsigned)p3 < uH;
       ta = (row3 && ina) ? ta : kInfKey;
       tb = (row3 && inb) ? tb : kInfKey;
 
@@ -273,7 +281,7 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       const int p4 = q - D3B;
       int ea = min3i(min3i(he[(u - 4) & 7][0], he[(u - 3) & 7][0], he[(u - 2) & 7][0]), he[(u - 1) & 7][0], he[u][0]);
       int eb = min3i(min3i(he[(u - 4) & 7][1], he[(u - 3) & 7][1], he[(u - 2) & 7][1]), he[(u - 1) & 7][1], he[u][1]);
-      const bool row4 = p4 >= 0 && p4 < H;
+      const bool row4 = (unsigned)p4 < uH;
       ea = (row4 && ina) ? ea : 0;
       eb = (row4 && inb) ? eb : 0;
       v3[u][0] = ea;
@@ -299,27 +307,18 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         const int c3a = v3[(u - 3) & 7][0], c3b = v3[(u - 3) & 7][1];
         oa = c3a <= kthr ? ma : c3a;
         ob = c3b <= kthr ? mb : c3b;
-        first_a = (o4row && outa && oa > kthr && first_a == kNoTop) ? o4 : first_a;
-        first_b = (o4row && outb && ob > kthr && first_b == kNoTop) ? o4 : first_b;
+        // rows arrive in order, so the first non-empty row is a running minimum
+        const int cand = o4row ? o4 : kNoTop;
+        first_a = min(first_a, (outa && oa > kthr) ? cand : kNoTop);
+        first_b = min(first_b, (outb && ob > kthr) ? cand : kNoTop);
       }
-
-      // One store site per row, for the map of the last stage asked for
-      // (each extra site would add conditional stores to every row).
-      int srow = o4, sa = oa, sb = ob;
-      if (last == 1) { srow = q; sa = va; sb = vb; }
-      else if (last == 2) { srow = p2; sa = w2a; sb = w2b; }
-      else if (last == 3) { srow = p4; sa = ea; sb = eb; }
-      if (srow >= ty0 && srow < ty0 + TH && srow < H) {
-        gint* o = dst + (size_t)srow * W;
-        if (outa) stk(o, ua, sa);
-        if (outb) stk(o, ub, sb);
-      }
+      const unsigned ro = (unsigned)o4 * W4;
+      stk(dst, (o4row && outa) ? ro + ua : sink, oa);
+      stk(dst, (o4row && outb) ? ro + ub : sink, ob);
     }
   }
-  if (last >= 5) {
-    if (outa && first_a != kNoTop) atomicMin(f.top + ca, first_a);
-    if (outb && first_b != kNoTop) atomicMin(f.top + cb, first_b);
-  }
+  if (outa && first_a != kNoTop) atomicMin(f.top + ca, first_a);
+  if (outb && first_b != kNoTop) atomicMin(f.top + cb, first_b);
 }
 
 template <int SHAPE, int RD, int TH>
