@@ -223,6 +223,12 @@ void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, voi
   for (int i = 0; i < n; ++i) gtot += (long long)cdiv(frames[i].W, r.gtw) * cdiv(frames[i].H, r.gth);
   auto* slow = reinterpret_cast<int32_t*>(base + off);
   off += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot));
+  long long ltot = 0;
+  for (int i = 0; i < n; ++i) ltot += (long long)cdiv(frames[i].W, r.ltw) * cdiv(frames[i].H, r.lth);
+  auto* ltab = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(sizeof(int32_t) * (size_t)ltot);
+  auto* gtab = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(sizeof(int32_t) * (size_t)gtot);
   int lt = 0, gt = 0, col = 0;
   for (int i = 0; i < n; ++i) {
     const int H = frames[i].H, W = frames[i].W;
@@ -256,6 +262,8 @@ void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, voi
   hdr->gt_cols = r.gtw;
   hdr->slow = slow;
   hdr->slow_cap = (int32_t)gtot;
+  hdr->ltab = ltab;
+  hdr->gtab = gtab;
 }
 
 size_t batch_bytes(const ipb_frame* frames, int n, const Resolved& r) {
@@ -263,8 +271,11 @@ size_t batch_bytes(const ipb_frame* frames, int n, const Resolved& r) {
   size_t cols = 0, gtot = 0;
   for (int i = 0; i < n; ++i) cols += (size_t)frames[i].W;
   for (int i = 0; i < n; ++i) gtot += (size_t)cdiv(frames[i].W, r.gtw) * cdiv(frames[i].H, r.gth);
+  size_t ltot = 0;
+  for (int i = 0; i < n; ++i) ltot += (size_t)cdiv(frames[i].W, r.ltw) * cdiv(frames[i].H, r.lth);
   total += align_up(sizeof(int32_t) * cols);
   total += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot));
+  total += align_up(sizeof(int32_t) * ltot) + align_up(sizeof(int32_t) * gtot);   // tile -> frame tables
   for (int i = 0; i < n; ++i)
     total += v4_bytes(frames[i].H, frames[i].W) + align_up(sizeof(float) * (size_t)frames[i].H * frames[i].W);
   return total;
@@ -343,7 +354,7 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
   kp.last_stage = last_stage;
   hipError_t e;
   if ((phase == -1 || phase == 0) && last_stage >= 5) {
-    e = launch_reset(src, max_cols, s);
+    e = launch_reset(src, std::max(max_cols, std::max(max_lt, max_gt)), s);
     if (e != hipSuccess) return hip_fail(e);
   }
   // Streaming kernels: one wave per tile, a grid of every tile (rounded up to

@@ -44,9 +44,12 @@ struct PlanHeader {
   int32_t gt_rows, gt_cols;   // phase-2 tile shape
   int32_t* slow;              // phase-2 tile queues, see SlowQueue
   int32_t slow_cap;           // capacity of each queue (phase-2 tiles of the launch)
-  int32_t pad[3];
+  int32_t pad0;
+  int32_t* ltab;              // frame index of every phase-1 tile (written by k_reset)
+  int32_t* gtab;              // frame index of every phase-2 tile (written by k_reset)
+  int32_t pad1[14];
 };
-static_assert(sizeof(PlanHeader) == 64, "plan header layout");
+static_assert(sizeof(PlanHeader) == 128, "plan header layout");
 static_assert(sizeof(FrameDesc) == 64, "frame descriptor layout");
 
 // Kernel parameters, passed by value.
@@ -112,7 +115,7 @@ __host__ __device__ inline int lds_queue_offset(int cap) { return 4 + 16 * cap; 
 __host__ __device__ inline int cell_queue_offset(int cap) { return 4 + 17 * cap; }
 
 // Host-side launchers (kernels.hip).
-hipError_t launch_reset(const FrameSource& src, int max_cols, hipStream_t s);
+hipError_t launch_reset(const FrameSource& src, int max_items, hipStream_t s);
 hipError_t launch_global_slow(const FrameSource& src, const KParams& kp, int stream_rows, int stream_cols,
                               int grid, hipStream_t s);
 int slow_subtiles(int stream_rows, int stream_cols);

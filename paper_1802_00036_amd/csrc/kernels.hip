@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_local(FrameSource src, KParams kp)
   const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
   for (int t = xcd_tile(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
     FrameDesc f;
-    if (src.plan) f = plan_frames(src.plan)[find_frame<true>(src.plan, t)];
+    if (src.plan) f = plan_frames(src.plan)[src.plan->ltab[t]];
     else f = src.single;
     const int lt = t - f.ltile0;
     const int tr = lt / f.lcols;
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_global(FrameSource src, KParams kp
   const int total = src.plan ? src.plan->gtiles : src.single_gtiles;
   for (int t = xcd_tile(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
     FrameDesc f;
-    if (src.plan) f = plan_frames(src.plan)[find_frame<false>(src.plan, t)];
+    if (src.plan) f = plan_frames(src.plan)[src.plan->gtab[t]];
     else f = src.single;
     const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(kThreads) void k_global_slow(FrameSource src, KPara
   for (int i = blockIdx.x; i < count * per; i += gridDim.x) {
     const int t = queue[i / per], j = i % per;
     FrameDesc f;
-    if (src.plan) f = plan_frames(src.plan)[find_frame<false>(src.plan, t)];
+    if (src.plan) f = plan_frames(src.plan)[src.plan->gtab[t]];
     else f = src.single;
     const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
@@ -642,8 +642,15 @@ __global__ __launch_bounds__(kThreads) void k_reset(FrameSource src) {
   int32_t* base = src.plan ? src.plan->top_base : src.single.top;
   const int n = src.plan ? src.plan->ncols : src.single.W;
   int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int gid = blockIdx.x * kThreads + threadIdx.x, stride = gridDim.x * kThreads;
   if (blockIdx.x == 0 && threadIdx.x < 4 && slow != nullptr) slow[threadIdx.x] = 0;
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) base[i] = kNoTop;
+  for (int i = gid; i < n; i += stride) base[i] = kNoTop;
+  // the frame of every tile, so that a tile's wave finds its frame with one load
+  if (src.plan) {
+    const PlanHeader* p = src.plan;
+    for (int i = gid; i < p->ltiles; i += stride) p->ltab[i] = find_frame<true>(p, i);
+    for (int i = gid; i < p->gtiles; i += stride) p->gtab[i] = find_frame<false>(p, i);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -674,8 +681,8 @@ int num_global_tiles() { return kNumGlobal; }
   X(1, 12, 32, 64) X(2, 12, 16, 64) X(3, 12, 32, 128) X(4, 12, 64, 64)
 #define IPB_GLOBAL_CASES(X) X(1, 32, 64) X(2, 16, 64) X(3, 48, 64) X(4, 16, 128)
 
-hipError_t launch_reset(const FrameSource& src, int max_cols, hipStream_t s) {
-  int grid = (max_cols + kThreads - 1) / kThreads;
+hipError_t launch_reset(const FrameSource& src, int max_items, hipStream_t s) {
+  int grid = (max_items + kThreads - 1) / kThreads;
   if (grid < 1) grid = 1;
   if (grid > 1024) grid = 1024;
   hipLaunchKernelGGL(k_reset, dim3(grid), dim3(kThreads), 0, s, src);

@@ -108,17 +108,6 @@ __device__ __forceinline__ FrameDesc uniform_frame(const FrameDesc& f) {
   return u;
 }
 
-template <bool LOCAL>
-__device__ __forceinline__ int find_frame_s(const PlanHeader* p, int t) {
-  const FrameDesc* f = reinterpret_cast<const FrameDesc*>(p + 1);
-  int lo = 0, hi = p->n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int start = LOCAL ? f[mid].ltile0 : f[mid].gtile0;
-    if (start <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Stage-2 kernel rows: row dy of the kernel is the centred interval
 // |dx| <= se_half(dy) (full, cross, diamond, circle).
@@ -327,7 +316,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(5))) voi
   const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
   for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
     FrameDesc f;
-    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[find_frame_s<true>(src.plan, t)];
+    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[src.plan->ltab[t]];
     else f = src.single;
     f = uniform_frame(f);
     const int lt = t - f.ltile0;
@@ -698,7 +687,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) voi
     FrameDesc f;
     int fidx = 0;
     if (src.plan) {
-      fidx = find_frame_s<false>(src.plan, t);
+      fidx = src.plan->gtab[t];
       f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx];
     } else {
       f = src.single;

@@ -127,9 +127,13 @@ def test_batch_plan_layout():
     lib.ipb_tile_shape(2, 0, ctypes.byref(rows), ctypes.byref(ccols))
     want_gt = sum(-(-h // rows.value) * -(-w // ccols.value) for h, w in shapes)
     assert (n.value, lt.value, gt.value, cols.value) == (4, want_lt, want_gt, sum(w for _, w in shapes))
-    # frame descriptors: 64-byte header then 64 bytes per frame
+    # frame descriptors: 128-byte header then 64 bytes per frame
     raw = np.frombuffer(plan.raw, dtype=np.uint8)
-    desc = raw[64:].reshape(len(shapes), 64)
+    assert pb == 128 + 64 * len(shapes)
+    desc = raw[128:].reshape(len(shapes), 64)
+    # the tile -> frame tables lie in the workspace
+    tabs = raw[56:72].copy().view(np.uint64)             # ltab, gtab
+    assert all(ws <= t < ws + nb for t in tabs)
     ptrs = desc[:, :32].copy().view(np.uint64)          # in, out, v4, top
     hw = desc[:, 32:48].copy().view(np.int32)            # H, W, ltile0, gtile0
     for i, (H, W) in enumerate(shapes):
