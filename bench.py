@@ -33,8 +33,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "frames/s and HBM GB/s at 375x1242 batched; p50/p99 latency under serving load"
 HBM_PEAK_GBPS = 8000.0
-# launch steps of one batch (ipb_complete_planned phases 0..4) and the kernel each launches
-PHASES = ["k_reset", "k_local_stream", "k_global_stream", "k_fill_cells+k_fill_dense+k_global_patched", "k_global_slow"]
+# launch steps of one batch (ipb_complete_planned phases 0..5) and the kernels each launches
+PHASES = ["k_reset", "k_local_stream", "k_fill_scan+k_fill_tiles", "k_global_stream",
+          "k_fill_cells+k_fill_dense+k_global_patched", "k_global_slow"]
 # algorithmic HBM bytes per pixel: stage-1 input read + stage-4 map write (phase 1);
 # stage-4 map read + output write (phase 2)
 BYTES_PER_PX = {"k_local_stream": 8, "k_global_stream": 8}

@@ -173,11 +173,17 @@ int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p,
  * phase: -1 = everything; else one launch step, in this order:
  *   0 reset the column tables and the tile queues;
  *   1 stages 1-4;
- *   2 stages 5-9 (streaming kernel: every tile, assuming the 31x31 fill
- *     changes nothing; tile quarters where it does are queued);
- *   3 the queued quarters: the fill at their empty cells, then stages 7-9
- *     again (streaming kernels only; no-op otherwise);
- *   4 tiles of frames under 3 rows or columns (streaming kernels only).
+ *   2 the default chain (Sec. III; Tables 2 and 3: 5x5 median, 5x5
+ *     Gaussian, the full extension) on the streaming kernels: the 31x31
+ *     fill of the cells that are empty after stage 5, written into the
+ *     stage-4 map ahead of phase 2 (no-op otherwise);
+ *   3 stages 5-9 (other chains on the streaming kernel: every tile,
+ *     assuming the 31x31 fill changes nothing; tile quarters where it does
+ *     are queued);
+ *   4 the queued quarters: the fill at their empty cells, then stages 7-9
+ *     again (streaming kernels, chains other than the default; no-op
+ *     otherwise);
+ *   5 tiles of frames under 3 rows or columns (streaming kernels only).
  * The split exists for per-kernel timing.  Allocates nothing, synchronises
  * nothing, reads no device memory on the host. */
 int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase,

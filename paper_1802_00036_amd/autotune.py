@@ -120,7 +120,7 @@ class _Timer:
 
             total = 0.0
             for r in range(reps + 1):
-                for ph in range(5):
+                for ph in range(6):
                     if ph in phases:
                         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                         a.record(s)
@@ -161,14 +161,14 @@ def tune(frames: Sequence[torch.Tensor], params: Optional[Params] = None, reps: 
     timer = _Timer(frames, outs, stream)
     best_l, t_l = None, None
     for tl in candidate_ids(1):
-        t = timer.time_us(dataclasses.replace(p0, tile_local=tl, tile_global=0), phases=(1,), reps=reps)
+        t = timer.time_us(dataclasses.replace(p0, tile_local=tl, tile_global=0), phases=(1, 2), reps=reps)
         if report is not None:
             report.append({"phase": 1, "tile": tl, "us": t})
         if t is not None and (t_l is None or t < t_l):
             best_l, t_l = tl, t
     best_g, t_g = None, None
     for tg in candidate_ids(2):
-        t = timer.time_us(dataclasses.replace(p0, tile_local=best_l or 0, tile_global=tg), phases=(2, 3, 4),
+        t = timer.time_us(dataclasses.replace(p0, tile_local=best_l or 0, tile_global=tg), phases=(3, 4, 5),
                           reps=reps)
         if report is not None:
             report.append({"phase": 2, "tile": tg, "us": t})

@@ -139,8 +139,7 @@ int cdiv(int a, int b) { return (a + b - 1) / b; }
 struct DeviceFacts {
   int cus = 0;
   int occ[3][8][2] = {};    // LDS kernels: [phase][tile id][halo 9/12]
-  int socc[3][8][16] = {};  // streaming kernels: [phase][tile id][shape * 4 + radius]
-  int slow_occ = 0;
+  int prefill_occ = 0;     // fill ahead of phase 2 (k_fill_tiles)
 };
 std::mutex g_dev_mu;
 DeviceFacts g_dev[64];
@@ -168,18 +167,10 @@ int resident(int dev, int phase, int tile, int halo) {
   return slot;
 }
 
-int stream_res(int dev, int phase, const Resolved& r) {
+int prefill_res(int dev) {
   std::lock_guard<std::mutex> g(g_dev_mu);
-  const int key = phase == 1 ? (r.kp.shape * 4 + r.kp.rd) : 0;
-  int& slot = g_dev[dev].socc[phase][phase == 1 ? r.ltile : r.gtile][key];
-  if (slot == 0) slot = stream_resident_blocks(phase, phase == 1 ? r.ltile : r.gtile, r.kp);
-  return slot;
-}
-
-int slow_res(int dev) {
-  std::lock_guard<std::mutex> g(g_dev_mu);
-  int& slot = g_dev[dev].slow_occ;
-  if (slot == 0) slot = slow_resident_blocks();
+  int& slot = g_dev[dev].prefill_occ;
+  if (slot == 0) slot = prefill_resident_blocks();
   return slot;
 }
 
@@ -219,12 +210,11 @@ void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, voi
   for (int i = 0; i < n; ++i) cols += frames[i].W;
   auto* top_base = reinterpret_cast<int32_t*>(base + off);
   off += align_up(sizeof(int32_t) * (size_t)cols);
-  long long gtot = 0;
+  long long gtot = 0, ltot = 0;
   for (int i = 0; i < n; ++i) gtot += (long long)cdiv(frames[i].W, r.gtw) * cdiv(frames[i].H, r.gth);
-  auto* slow = reinterpret_cast<int32_t*>(base + off);
-  off += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot));
-  long long ltot = 0;
   for (int i = 0; i < n; ++i) ltot += (long long)cdiv(frames[i].W, r.ltw) * cdiv(frames[i].H, r.lth);
+  auto* slow = reinterpret_cast<int32_t*>(base + off);
+  off += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot, (int)ltot));
   auto* ltab = reinterpret_cast<int32_t*>(base + off);
   off += align_up(sizeof(int32_t) * (size_t)ltot);
   auto* gtab = reinterpret_cast<int32_t*>(base + off);
@@ -274,7 +264,7 @@ size_t batch_bytes(const ipb_frame* frames, int n, const Resolved& r) {
   size_t ltot = 0;
   for (int i = 0; i < n; ++i) ltot += (size_t)cdiv(frames[i].W, r.ltw) * cdiv(frames[i].H, r.lth);
   total += align_up(sizeof(int32_t) * cols);
-  total += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot));
+  total += align_up(sizeof(int32_t) * slow_queue_ints((int)gtot, (int)ltot));
   total += align_up(sizeof(int32_t) * ltot) + align_up(sizeof(int32_t) * gtot);   // tile -> frame tables
   for (int i = 0; i < n; ++i)
     total += v4_bytes(frames[i].H, frames[i].W) + align_up(sizeof(float) * (size_t)frames[i].H * frames[i].W);
@@ -339,11 +329,14 @@ FrameSource single_source(const float* in, int H, int W, float* out, void* ws, c
 
 size_t frame_ws_bytes(int H, int W, const Resolved& r) {
   const size_t gtiles = (size_t)cdiv(W, r.gtw) * cdiv(H, r.gth);
+  const size_t ltiles = (size_t)cdiv(W, r.ltw) * cdiv(H, r.lth);
   return v4_bytes(H, W) + align_up(sizeof(float) * (size_t)H * W) + align_up(sizeof(int32_t) * (size_t)W) +
-         align_up(sizeof(int32_t) * slow_queue_ints((int)gtiles));
+         align_up(sizeof(int32_t) * slow_queue_ints((int)gtiles, (int)ltiles));
 }
 
-// Launch the phases of a frame source: 0 = reset, 1 = stages 1-4, 2 = stages 5-9.
+// Launch the phases of a frame source (-1: all; ipb_complete_planned lists
+// them): 0 reset, 1 stages 1-4, 2 the fill of stage 6 ahead of phase 2,
+// 3 stages 5-9, 4 the second pass of queued quarters, 5 tiny frames.
 int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last_stage, int max_lt, int max_gt,
                   int max_cols, bool persistent, hipStream_t s) {
   int dev = 0;
@@ -352,6 +345,10 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
   const int cus = g_dev[dev].cus;
   KParams kp = r.kp;
   kp.last_stage = last_stage;
+  // the default chain on streaming kernels: the fill runs ahead of phase 2,
+  // which then needs no second pass
+  const bool fast = r.lstream && r.gstream && fast_chain(kp);
+  const bool prefill = fast && kp.extrapolate;
   hipError_t e;
   if ((phase == -1 || phase == 0) && last_stage >= 5) {
     e = launch_reset(src, std::max(max_cols, std::max(max_lt, max_gt)), s);
@@ -368,14 +365,22 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
     if (e != hipSuccess) return hip_fail(e);
   }
   if (last_stage < 5) return IPB_OK;
-  if (phase == -1 || phase == 2) {
+  if ((phase == -1 || phase == 2) && prefill) {
+    // one scanning wave per phase-1 tile (those of the first tile row work);
+    // one workgroup per queued tile, at most the resident ones
+    const int tgrid = std::max(1, std::min(max_lt, prefill_res(dev) * cus));
+    e = launch_prefill(src, kp, r.lth, max_lt, tgrid, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (phase == -1 || phase == 3) {
     int grid = max_gt;
     if (r.gstream) grid = (grid + 7) / 8 * 8;
     else if (persistent) grid = std::min(grid, resident(dev, 2, r.gtile, 0) * cus);
-    e = r.gstream ? launch_global_stream(src, kp, r.gtile, grid, s) : launch_global(src, kp, r.gtile, grid, s);
+    e = r.gstream ? launch_global_stream(src, kp, r.gtile, fast, grid, s)
+                  : launch_global(src, kp, r.gtile, grid, s);
     if (e != hipSuccess) return hip_fail(e);
   }
-  if ((phase == -1 || phase == 3) && r.gstream) {
+  if ((phase == -1 || phase == 4) && r.gstream && !fast) {
     // queued quarters (at most four per tile) and cells (at most
     // 4 kCellEmpty per tile); grids of at most 32 waves per CU
     const int rgrid = std::max(1, std::min(4 * max_gt, 32 * cus));
@@ -383,7 +388,7 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
     e = launch_global_repair(src, kp, r.gtile, rgrid, cgrid, s);
     if (e != hipSuccess) return hip_fail(e);
   }
-  if ((phase == -1 || phase == 4) && r.gstream) {
+  if ((phase == -1 || phase == 5) && r.gstream) {
     const int per = slow_subtiles(r.gth, r.gtw);
     // frames under 3 rows or columns are rare and small: one workgroup per CU
     const int sgrid = std::max(1, std::min(max_gt * per, cus));
@@ -524,7 +529,7 @@ int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase, i
   Resolved r;
   int st = resolve(p, &r);
   if (st != IPB_OK) return st;
-  if (plan_dev == nullptr || phase < -1 || phase > 4) return IPB_ERR_INVALID_ARG;
+  if (plan_dev == nullptr || phase < -1 || phase > 5) return IPB_ERR_INVALID_ARG;
   if (max_tiles_local < 1 || max_tiles_global < 1 || max_cols < 1) return IPB_ERR_INVALID_ARG;
   FrameSource src;
   std::memset(&src, 0, sizeof(src));

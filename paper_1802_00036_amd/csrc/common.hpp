@@ -30,7 +30,11 @@ struct FrameDesc {
   int32_t lcols;      // phase-1 tiles per row of tiles
   int32_t gcols;      // phase-2 tiles per row of tiles
   float* v6p;         // stage-6 values of the cells that were empty after stage 5 (H * W floats;
-                      // only those cells are written and read)
+                      // only those cells are written and read).  Its first
+                      // ceil(H / phase-1 tile rows) * W ints hold the phase-1
+                      // column records (first non-empty and last empty row of
+                      // each tile column) that the fill ahead of phase 2 reads;
+                      // the general second pass overwrites them freely.
 };
 
 // Device-resident launch plan: header followed by n FrameDesc.
@@ -91,7 +95,8 @@ struct FrameSource {
   int32_t slow_cap;
 };
 
-// Queues of the streaming phase 2, in the workspace (cap = phase-2 tiles):
+// Queues of the streaming kernels, in the workspace (gcap = phase-2 tiles,
+// lcap = phase-1 tiles of the launch); eight counters, then the entries:
 //   slow[0]   quarters whose input rows still hold an empty cell after the
 //             extension and whose own rows hold at most kCellEmpty empty
 //             cells (their cells go to the cell queue);
@@ -104,15 +109,31 @@ struct FrameSource {
 //             (k_fill_cells): two ints, the frame index and y * W + x;
 //   slow[1]   tiles of frames under 3 rows or columns (launch tile ids),
 //             recomputed by the LDS kernel;
-//   slow[4 ..)              the first queue (8 cap ints), the dense queue
-//                           (8 cap ints), the tiny-frame queue (cap), then
-//                           the cell queue (8 kCellEmpty cap ints).
+//   slow[4]   phase-1 tiles holding a cell that is empty after the
+//             extension, for the fill ahead of phase 2 (k_fill_scan,
+//             k_fill_tiles): two ints, the launch tile id and the frame index;
+//   slow[8 ..)              the first queue (8 gcap ints), the dense queue
+//                           (8 gcap ints), the tiny-frame queue (gcap), the
+//                           cell queue (8 kCellEmpty gcap ints), then the
+//                           phase-1 tile queue (2 lcap ints).
+// The first three queues and the cell queue serve the general phase 2 (its
+// second pass); the phase-1 tile queue serves the default chain, whose fill
+// runs before phase 2.
 constexpr int kCellEmpty = 32;
-__host__ __device__ inline size_t slow_queue_ints(int cap) { return 4 + (17 + 8 * kCellEmpty) * (size_t)cap; }
-__host__ __device__ inline int sparse_queue_offset(int) { return 4; }
-__host__ __device__ inline int dense_queue_offset(int cap) { return 4 + 8 * cap; }
-__host__ __device__ inline int lds_queue_offset(int cap) { return 4 + 16 * cap; }
-__host__ __device__ inline int cell_queue_offset(int cap) { return 4 + 17 * cap; }
+constexpr int kQueueHead = 8;
+__host__ __device__ inline size_t slow_queue_ints(int gcap, int lcap) {
+  return kQueueHead + (17 + 8 * kCellEmpty) * (size_t)gcap + 2 * (size_t)lcap;
+}
+__host__ __device__ inline int sparse_queue_offset(int) { return kQueueHead; }
+__host__ __device__ inline int dense_queue_offset(int cap) { return kQueueHead + 8 * cap; }
+__host__ __device__ inline int lds_queue_offset(int cap) { return kQueueHead + 16 * cap; }
+__host__ __device__ inline int cell_queue_offset(int cap) { return kQueueHead + 17 * cap; }
+__host__ __device__ inline int fill_queue_offset(int cap) { return kQueueHead + (17 + 8 * kCellEmpty) * cap; }
+
+// Cells that the fill ahead of phase 2 wrote into the stage-4 map carry the
+// sign bit: readers of stage-5 values take them as empty, the phase-2
+// kernel clears the bit.
+constexpr int kFillTag = (int)0x80000000u;
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_reset(const FrameSource& src, int max_items, hipStream_t s);
@@ -129,10 +150,15 @@ int stream_global_tile_cols(int id);
 bool stream_local_supported(int shape, int rd, int rc, int rf);
 bool stream_global_supported(int rm, int rg);
 hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s);
-hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s);
+hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, bool fast, int grid,
+                                hipStream_t s);
 hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, int cell_grid,
                                 hipStream_t s);
-int stream_resident_blocks(int phase, int tile_id, const KParams& kp);
+hipError_t launch_prefill(const FrameSource& src, const KParams& kp, int local_rows, int scan_grid, int tile_grid,
+                          hipStream_t s);
+bool fast_chain(const KParams& kp);
+int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast);
+int prefill_resident_blocks();
 hipError_t launch_local(const FrameSource& src, const KParams& kp, int tile_id, int halo,
                         int grid, hipStream_t s);
 hipError_t launch_global(const FrameSource& src, const KParams& kp, int tile_id,

@@ -637,13 +637,13 @@ __global__ __launch_bounds__(kThreads) void k_global_slow(FrameSource src, KPara
 }
 
 // Column tables of every frame of a launch: reset to "no non-empty row";
-// empty the queue of tiles that need the 31x31 fill.
+// empty the queues of the 31x31 fill.
 __global__ __launch_bounds__(kThreads) void k_reset(FrameSource src) {
   int32_t* base = src.plan ? src.plan->top_base : src.single.top;
   const int n = src.plan ? src.plan->ncols : src.single.W;
   int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int gid = blockIdx.x * kThreads + threadIdx.x, stride = gridDim.x * kThreads;
-  if (blockIdx.x == 0 && threadIdx.x < 4 && slow != nullptr) slow[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kQueueHead && slow != nullptr) slow[threadIdx.x] = 0;
   for (int i = gid; i < n; i += stride) base[i] = kNoTop;
   // the frame of every tile, so that a tile's wave finds its frame with one load
   if (src.plan) {

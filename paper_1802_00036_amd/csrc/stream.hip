@@ -57,12 +57,28 @@ __device__ __forceinline__ int ldk(gcint* row, unsigned off) { return *(gcint*)(
 __device__ __forceinline__ float ldf(gcfloat* row, unsigned off) { return *(gcfloat*)((gcchar*)row + off); }
 __device__ __forceinline__ void stk(gint* row, unsigned off, int v) { *(gint*)((gchar*)row + off) = v; }
 __device__ __forceinline__ float val(int k) { return __int_as_float(k); }
+__device__ __forceinline__ void st16(gchar* base, unsigned off, unsigned short v) {
+  *(__attribute__((address_space(1))) unsigned short*)(base + off) = v;
+}
 
 // lane i receives lane i-1's value (lane 0 receives 0; its neighbours are
 // outside the tile's input columns and never feed an output)
 __device__ __forceinline__ int from_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 // lane i receives lane i+1's value (lane 63 receives 0)
 __device__ __forceinline__ int from_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+// Max over the wave of non-negative values, as a uniform value: prefix
+// maxima within rows of 16 lanes (row_shr 1, 2, 4, 8), then across rows
+// (row_bcast 15 and 31); lane 63 ends with the whole wave's max.  Lanes
+// without a source contribute 0.
+__device__ __forceinline__ int wave_max_nonneg(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
 __device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
 __device__ __forceinline__ int min3i(int a, int b, int c) { return min(min(a, b), c); }
 __device__ __forceinline__ int clampi_s(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -133,6 +149,15 @@ __device__ __forceinline__ void for_slots(F&& f) {
   for_slots_impl(f, std::make_integer_sequence<int, 8>{});
 }
 
+// Phase-1 column record of a tile column: the first non-empty row relative
+// to the tile's first row (low 16 bits; kRecNone: none) and whether an empty
+// row follows it in the tile (high 16 bits: kRecHole, else kRecNone).
+constexpr int kRecNone = 0xffff;
+constexpr int kRecHole = 1;
+__device__ __forceinline__ unsigned short record_first(int first, int ty0) {
+  return (unsigned short)(first == kNoTop ? kRecNone : first - ty0);
+}
+
 // ---------------------------------------------------------------------------
 // Phase 1, streaming: stages 1-4 for 108 x TH output cells per wave.
 constexpr int kLocalHalo = 10;                         // >= RD + 2 + 2 + 3 for RD <= 3
@@ -179,6 +204,12 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   }
   int first_a = kNoTop, first_b = kNoTop;
   gint* dst = gw(f.v4);
+  // column records for the fill ahead of phase 2 (pack_record): the hole
+  // half is set here to "none" and overwritten on the rare rows that hold a
+  // hole; the first-row half is written at the end of the tile
+  gchar* rec = (gchar*)(char*)f.v6p + 4 * (size_t)(ty0 / TH) * W;   // uniform row base; lanes add ua / ub
+  if (outa) st16(rec, ua + 2, kRecNone);
+  if (outb) st16(rec, ub + 2, kRecNone);
   gcfloat* in = gcf(f.in);
   const unsigned W4 = 4u * (unsigned)W;
   const unsigned sink = (unsigned)H * W4;                 // scratch slot past the stage-4 map
@@ -300,6 +331,13 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         const int cand = o4row ? o4 : kNoTop;
         first_a = min(first_a, (outa && oa > kthr) ? cand : kNoTop);
         first_b = min(first_b, (outb && ob > kthr) ? cand : kNoTop);
+        // an empty cell below the column's first non-empty row of the tile
+        const bool hole_a = o4row && outa && oa <= kthr && first_a < o4;
+        const bool hole_b = o4row && outb && ob <= kthr && first_b < o4;
+        if (__builtin_expect(__ballot(hole_a || hole_b) != 0, 0)) {
+          if (hole_a) st16(rec, ua + 2, kRecHole);
+          if (hole_b) st16(rec, ub + 2, kRecHole);
+        }
       }
       const unsigned ro = (unsigned)o4 * W4;
       stk(dst, (o4row && outa) ? ro + ua : sink, oa);
@@ -308,6 +346,8 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   }
   if (outa && first_a != kNoTop) atomicMin(f.top + ca, first_a);
   if (outb && first_b != kNoTop) atomicMin(f.top + cb, first_b);
+  if (outa) st16(rec, ua, record_first(first_a, ty0));
+  if (outb) st16(rec, ub, record_first(first_b, ty0));
 }
 
 template <int SHAPE, int RD, int TH>
@@ -354,12 +394,16 @@ __device__ __forceinline__ double hsum5(double wc, double w1, double w2, int m2,
   return fma(wc, (double)val(c), fma(w1, s1, w2 * s2));
 }
 
-// Stages 5-9 of one streaming tile (TH x 120 output cells).  First pass
-// (PATCHED false): the stage-6 map is taken to equal the stage-5 map; tiles
-// where that does not hold are queued by quarter.  Second pass (PATCHED
-// true, one quarter): cells empty after stage 5 read their stage-6 value
-// from f.v6p (written by k_fill_cells / k_fill_dense).  s_cells: LDS lists
-// of the first kCellEmpty empty cells of each quarter (first pass only).
+// Stages 5-9 of one streaming tile (TH x 120 output cells).
+// FAST (the default chain): the fill of stage 6 already ran (k_fill_scan,
+// k_fill_tiles) and wrote its values into the stage-4 map, tagged; the pass
+// reads stage-6 values directly.
+// Otherwise, first pass (PATCHED false): the stage-6 map is taken to equal
+// the stage-5 map; tiles where that does not hold are queued by quarter.
+// Second pass (PATCHED true, one quarter): cells empty after stage 5 read
+// their stage-6 value from f.v6p (written by k_fill_cells / k_fill_dense).
+// s_cells: LDS lists of the first kCellEmpty empty cells of each quarter
+// (first pass only).
 template <int TH, bool PATCHED, bool FAST>
 __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int fidx, int gt,
                                                    int ty0, int tx0, int lane, int32_t* slow, int cap, int* s_cells) {
@@ -477,14 +521,22 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
     constexpr int u = decltype(u_tag)::value;            // ring slot: a constant
     constexpr bool WARM = decltype(warm_tag)::value;     // the first block: r = u
     const int q = q0 + r;
-    int va = detach(pa[u]), vb = detach(pb[u]);
+    // FAST: cells the fill ahead of this pass completed carry kFillTag
+    int va, vb;
+    if constexpr (FAST) {
+      va = pa[u] & ~kFillTag;
+      vb = pb[u] & ~kFillTag;
+    } else {
+      va = detach(pa[u]);
+      vb = detach(pb[u]);
+    }
     if (PATCHED) {
       va = va <= kthr ? detach(ppa[u]) : va;
       vb = vb <= kthr ? detach(ppb[u]) : vb;
     }
     fetch(r + 8, u);
     if (FAST || (q >= 0 && q < H)) {
-      if (!PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
+      if (!FAST && !PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
         // row q is an input row of quarter k when k*QR - 4 <= q - ty0 < (k+1)*QR + 4
         const int rel = q - ty0;
 #pragma unroll
@@ -670,11 +722,6 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
   }
 }
 
-// The default chain (5x5 median, 5x5 Gaussian, every stage) takes the
-// kernels' FAST variant.
-inline bool fast_chain(const KParams& kp) {
-  return kp.rm == 2 && kp.rg == 2 && kp.last_stage == 9 && kp.blur == 0 && kp.ext_rows == 0;
-}
 
 template <int TH, bool FAST>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) void k_global_stream(FrameSource src, KParams kp) {
@@ -710,41 +757,49 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) voi
 // unaffected.
 constexpr int kFillRad = 15;   // largest large-fill radius (31x31)
 
+// The largest stage-5 key of the (2 rl + 1)^2 window around cell (y, x),
+// in every lane of the wave (cells outside the image ignored; cells the
+// fill ahead of phase 2 already wrote carry kFillTag, a negative key, and
+// count as empty).  Lane l covers window column (l mod 32) - rl and, for
+// l < 32, the window rows -rl .. -rl + 15, else the next 16.
+__device__ __forceinline__ int window_max(const FrameDesc& f, const KParams& kp, int y, int x, int lane) {
+  const int H = f.H, W = f.W, rl = kp.rl;
+  const int dx = (lane & 31) - rl;
+  const bool colw = (lane & 31) <= 2 * rl;
+  const int dy0 = 16 * (lane >> 5) - rl;
+  gcint* v4 = gc(f.v4);
+  const int gx = x + dx;
+  const bool colin = colw && gx >= 0 && gx < W;
+  const int xc = clampi_s(gx, 0, W - 1);
+  const int tt = kp.extrapolate ? gc(f.top)[xc] : H;   // stage 5: rows above the top read the top
+  int w[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int yc = clampi_s(y + dy0 + k, 0, H - 1);
+    w[k] = v4[(size_t)v5_row(yc, tt, H, kp.ext_rows) * W + xc];
+  }
+  int m = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int gy = y + dy0 + k;
+    m = max(m, (colin && dy0 + k <= rl && gy >= 0 && gy < H) ? w[k] : 0);
+  }
+  return wave_max_nonneg(m);
+}
+
 __global__ __launch_bounds__(kLanes) void k_fill_cells(FrameSource src, KParams kp) {
   const int lane = threadIdx.x;
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int count = min(slow[3], 4 * kCellEmpty * cap);
   const int32_t* cells = slow + cell_queue_offset(cap);
-  const int rl = kp.rl;
-  const int dx = (lane & 31) - rl;
-  const bool colw = (lane & 31) <= 2 * rl;
-  const int dy0 = 16 * (lane >> 5) - rl;
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int fidx = cells[2 * i], pos = cells[2 * i + 1];
     FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
     f = uniform_frame(f);
-    const int H = f.H, W = f.W;
+    const int W = f.W;
     const int y = uni(pos / W), x = uni(pos - (pos / W) * W);
-    gcint* v4 = gc(f.v4);
-    const int gx = x + dx;
-    const bool colin = colw && gx >= 0 && gx < W;
-    const int xc = clampi_s(gx, 0, W - 1);
-    const int tt = kp.extrapolate ? gc(f.top)[xc] : H;   // stage 5: rows above the top read the top
-    int w[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int yc = clampi_s(y + dy0 + k, 0, H - 1);
-      w[k] = v4[(size_t)v5_row(yc, tt, H, kp.ext_rows) * W + xc];
-    }
-    int m = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int gy = y + dy0 + k;
-      m = max(m, (colin && dy0 + k <= rl && gy >= 0 && gy < H) ? w[k] : 0);
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+    const int m = window_max(f, kp, y, x, lane);
     if (lane == 0) gw(f.v6p)[(size_t)pos] = m;
   }
 }
@@ -766,20 +821,136 @@ __device__ __forceinline__ void vhgw31(const int* a, int* out) {
   out[31] = pre[30];
 }
 
-// Phase 2, queued quarters with many empty cells, step 1: the same fill
-// values, computed separably for the whole quarter by a workgroup of four
-// waves.  The stage-5 values of the quarter's rows +- rl and columns +- rl
-// go to LDS; their horizontal window maxima (van Herk/Gil-Werman for the
-// 31-wide window) replace them in place; each empty cell takes the
-// vertical max of those (for the 31-row window: the rows all the quarter's
-// windows share, then the prefix and suffix maxima at both ends).
+// The fill computed separably for a region of nr <= QR rows (from y0) and
+// ncols <= 128 columns (from x0) by a workgroup of four waves.  The stage-5
+// values of the region's rows +- rl and columns +- rl go to LDS (cells
+// outside the image and tagged cells as 0, which no max selects over a
+// non-empty value); their horizontal window maxima (van Herk/Gil-Werman for
+// the 31-wide window) replace them in place; each cell of the region that is
+// empty after stage 5 takes the vertical max of those (for the 31-row window:
+// the rows all the region's windows share, then the prefix and suffix maxima
+// at both ends) and is handed to out(y, x, value).
 constexpr int kDW = kGlobalTW + 2 * kFillRad + 8;    // 158 staged columns (4 runs of 32 outputs + 30)
 constexpr int kDenseThreads = 256;
 
+template <int QR, class Out>
+__device__ __forceinline__ void fill_region(const FrameDesc& f, const KParams& kp, int y0, int nr, int x0, int ncols,
+                                            int* S, int* s_top, int tid, Out&& out) {
+  static_assert(QR + 2 * kFillRad <= kDenseThreads / 4, "one row of 128 horizontal maxima per four threads");
+  const int H = f.H, W = f.W, rl = kp.rl;
+  const int kthr = key(kp.thr);
+  gcint* v4 = gc(f.v4);
+  const int sr = nr + 2 * rl;
+  __syncthreads();                                    // LDS of the previous region is no longer read
+  if (tid < kDW) {                                    // column tops of the staged columns (>= H: none)
+    const int x = clampi_s(x0 - rl + tid, 0, W - 1);
+    s_top[tid] = kp.extrapolate ? gc(f.top)[x] : H;
+  }
+  __syncthreads();
+  {
+    // the loads of a thread in batches of 13, each batch in flight at once
+    // (staged rows past sr load a clamped cell and are not stored)
+    constexpr int PER = ((QR + 2 * kFillRad) * kDW + kDenseThreads - 1) / kDenseThreads;
+    constexpr int B = 13;
+#pragma unroll 1
+    for (int k0 = 0; k0 < PER; k0 += B) {
+      int vals[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = tid + (k0 + k) * kDenseThreads;
+        const int rq = idx / kDW, cc = idx - rq * kDW;
+        const int rr = min(rq, sr - 1);
+        const int x = clampi_s(x0 - rl + cc, 0, W - 1), y = clampi_s(y0 - rl + rr, 0, H - 1);
+        vals[k] = ldk(v4, 4u * ((unsigned)v5_row(y, s_top[cc], H, kp.ext_rows) * (unsigned)W + (unsigned)x));
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = tid + (k0 + k) * kDenseThreads;
+        const int rr = idx / kDW, cc = idx - rr * kDW;
+        const int gx = x0 - rl + cc, gy = y0 - rl + rr;
+        if (k0 + k < PER && rr < sr) S[idx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? max(vals[k], 0) : 0;
+      }
+    }
+  }
+  __syncthreads();
+  // the region's cells that are empty after stage 5, one column per thread
+  // (bit r: row y0 + r), taken before the staged values are overwritten
+  unsigned emask = 0u;
+  if (tid < ncols) {
+    for (int r = 0; r < nr; ++r)
+      if (S[(rl + r) * kDW + rl + tid] <= kthr) emask |= 1u << r;
+  }
+  // horizontal window maxima of 128 (>= ncols) columns, written over the
+  // staged values once every row has been read
+  {
+    const int rr = tid >> 2, j0 = (tid & 3) * 32;
+    const bool act = rr < sr;
+    int o[32];
+    if (act) {
+      if (rl == kFillRad) {
+        int a[62];
+#pragma unroll
+        for (int c = 0; c < 62; ++c) a[c] = S[rr * kDW + j0 + c];
+        vhgw31(a, o);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) {
+          const int* p = S + rr * kDW + j0 + c;
+          int m = p[0];
+          for (int d = 1; d <= 2 * rl; ++d) m = max(m, p[d]);
+          o[c] = m;
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 32; ++c) S[rr * kDW + j0 + c] = o[c];
+    }
+  }
+  __syncthreads();
+  // vertical max at the empty cells of the region, one column per thread.
+  // Row r takes rows r .. r + 2 rl; when 2 rl >= QR - 2 they split into rows
+  // r .. QR - 2 (a suffix maximum), QR - 1 .. 2 rl (shared by every row) and
+  // 2 rl + 1 .. 2 rl + r (a prefix maximum).  Staged rows past sr only feed
+  // rows past nr.
+  static_assert(QR <= 32, "one bit per row");
+  if (tid < ncols && emask != 0u) {
+    const int c = tid;
+    const int gx = x0 + c;
+    if (2 * rl >= QR - 2) {
+      int mid = 0;
+      for (int d = QR - 1; d <= 2 * rl; ++d) mid = max(mid, S[d * kDW + c]);
+      int lo[QR];
+      int acc = 0;
+      lo[QR - 1] = 0;
+#pragma unroll
+      for (int r = QR - 2; r >= 0; --r) {
+        acc = max(acc, S[r * kDW + c]);
+        lo[r] = acc;
+      }
+      int hi = 0;
+#pragma unroll
+      for (int r = 0; r < QR; ++r) {
+        if (r > 0) hi = max(hi, S[(2 * rl + r) * kDW + c]);
+        if ((emask >> r) & 1u) out(y0 + r, gx, max(max(mid, lo[r]), hi));
+      }
+    } else {
+      for (int r = 0; r < nr; ++r) {
+        if (((emask >> r) & 1u) == 0u) continue;
+        int m = 0;
+        for (int d = 0; d <= 2 * rl; ++d) m = max(m, S[(r + d) * kDW + c]);
+        out(y0 + r, gx, m);
+      }
+    }
+  }
+}
+
+// Phase 2, queued quarters with many empty cells, step 1: the same fill
+// values, computed separably for the whole quarter (fill_region).
 template <int TH>
 __global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, KParams kp) {
   constexpr int QR = TH / 4, SR = QR + 2 * kFillRad;
-  static_assert(SR <= kDenseThreads / 4, "one row of 128 horizontal maxima per four threads");
   __shared__ int S[SR * kDW];
   __shared__ int s_top[kDW];
   const int tid = threadIdx.x;
@@ -787,108 +958,261 @@ __global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, K
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int count = min(slow[2], 4 * cap);
   const int32_t* queue = slow + dense_queue_offset(cap);
-  const int rl = kp.rl;
-  const int kthr = key(kp.thr);
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int fidx = queue[2 * i], tq = queue[2 * i + 1];
     const int gt = tq & ((1 << 27) - 1), qk = (unsigned)tq >> 27;
     FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
     f = uniform_frame(f);
-    const int H = f.H, W = f.W;
     const int tr = gt / f.gcols;
     const int y0 = tr * TH + qk * QR, tx0 = (gt - tr * f.gcols) * kGlobalTW;
-    gcint* v4 = gc(f.v4);
+    const int nr = min(QR, f.H - y0), ncols = min(kGlobalTW, f.W - tx0);
+    if (nr <= 0) continue;                      // a quarter past the last row (queued for its input rows)
     gint* v6p = gw(f.v6p);
-    const int sr = QR + 2 * rl;
-    __syncthreads();                                    // LDS of the previous quarter is no longer read
-    if (tid < kDW) {                                    // column tops of the staged columns (>= H: none)
-      const int x = clampi_s(tx0 - rl + tid, 0, W - 1);
-      s_top[tid] = kp.extrapolate ? gc(f.top)[x] : H;
+    const int W = f.W;
+    fill_region<QR>(f, kp, y0, nr, tx0, ncols, S, s_top, tid,
+                    [&](int y, int x, int m) { v6p[(size_t)y * W + x] = m; });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fill of stage 6 ahead of phase 2 (the default chain with the streaming
+// phase 1).  After phase 1 every column's top is final, so the cells empty
+// after stage 5 are known: in a phase-1 tile column they are
+//   - the empty rows after its first non-empty row (holes: such rows lie at
+//     or below the column's top), and
+//   - the rows before its first non-empty row (all of them when there is
+//     none) when the column's top lies in a tile above or the column has no
+//     top (the extension then leaves them empty).
+// Their fill values go into the stage-4 map itself, tagged (kFillTag):
+// stage-5 reads of other fills take a tagged cell as empty, as it was, and
+// phase 2 reads stage-6 values with the tag cleared.  Every cell belongs to
+// one phase-1 tile, whose workgroup alone writes it.
+
+// Whether a tile column's record holds such a cell, given the
+// column's top (>= H: none) and the tile's first row.
+__device__ __forceinline__ bool record_needs_fill(int rec, int top, int y0, int H) {
+  const int first = rec & 0xffff;
+  const bool lead = (top >= H || top < y0) && first != 0;
+  const bool hole = ((unsigned)rec >> 16) == kRecHole;
+  return lead || hole;
+}
+
+// One wave per column of phase-1 tiles (the waves of the first tile row's
+// tiles) walks the records of every tile row, eight tile rows at a time, and
+// queues the tiles that hold such a cell: the launch tile id and the frame
+// index.  Frames under 3 rows or columns are left to phase 2, which
+// recomputes them whole.
+__global__ __launch_bounds__(kLanes) void k_fill_scan(FrameSource src, KParams kp, int lth) {
+  const int lane = threadIdx.x;
+  const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
+  int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int gcap = src.plan ? src.plan->slow_cap : src.slow_cap;
+  int32_t* queue = slow + fill_queue_offset(gcap);
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int fidx = src.plan ? src.plan->ltab[t] : 0;
+    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
+    f = uniform_frame(f);
+    const int lt = t - f.ltile0;
+    const int H = f.H, W = f.W;
+    if (lt >= f.lcols || H < 3 || W < 3) continue;
+    const int x0 = lt * kLocalTW;
+    const int xa = x0 + lane, xb = x0 + kLanes + lane;
+    const bool ina = xa < W, inb = kLanes + lane < kLocalTW && xb < W;
+    const int xac = min(xa, W - 1), xbc = min(xb, W - 1);
+    gcint* top = gc(f.top);
+    gcint* rec = gc(f.v6p);
+    const int ta = top[xac], tb = top[xbc];
+    const int ntr = (H + lth - 1) / lth;
+    for (int tr0 = 0; tr0 < ntr; tr0 += 8) {
+      int ra[8], rb[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const size_t row = (size_t)min(tr0 + k, ntr - 1) * W;
+        ra[k] = rec[row + xac];
+        rb[k] = rec[row + xbc];
+      }
+      unsigned need = 0u;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int y0 = (tr0 + k) * lth;
+        const bool nd = (ina && record_needs_fill(ra[k], ta, y0, H)) || (inb && record_needs_fill(rb[k], tb, y0, H));
+        if (tr0 + k < ntr && __ballot(nd) != 0) need |= 1u << k;
+      }
+      if (need == 0u) continue;
+      int pos = 0;
+      if (lane == 0) pos = atomicAdd(slow + 4, __popc(need));
+      pos = __shfl(pos, 0) + __popc(need & ((1u << (lane & 7)) - 1u));
+      if (lane < 8 && ((need >> lane) & 1u) && pos < total) {
+        queue[2 * pos] = f.ltile0 + (tr0 + lane) * f.lcols + lt;
+        queue[2 * pos + 1] = fidx;
+      }
+    }
+  }
+}
+
+// bits of the bands (kBandRows rows) that rows lo .. hi of a tile touch
+constexpr int kBandRows = 32;
+__device__ __forceinline__ unsigned band_bits(int lo, int hi) {
+  return (2u << (hi / kBandRows)) - (1u << (lo / kBandRows));
+}
+constexpr int kFillSparse = 48;   // cells of a tile filled one by one; beyond: per band, separably
+constexpr int kFillScan = 2048;   // hole rows of a tile checked one by one; beyond: per band, separably
+
+// window_max for up to NC cells of one phase-1 tile at once (pos: y * W + x,
+// nc of them valid), every load issued before the first is used; the tops
+// come from s_top, which holds those of columns xs0 .. xs0 + kDW - 1
+// (clamped into the image).
+template <int NC>
+__device__ __forceinline__ void window_max_n(const FrameDesc& f, const KParams& kp, const int* pos, int nc,
+                                             const int* s_top, int xs0, int lane, int* m_out) {
+  const int H = f.H, W = f.W, rl = kp.rl;
+  const int dx = (lane & 31) - rl;
+  const bool colw = (lane & 31) <= 2 * rl;
+  const int dy0 = 16 * (lane >> 5) - rl;
+  gcint* v4 = gc(f.v4);
+  int w[NC][16], yk[NC];
+  bool colin[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int p = pos[k < nc ? k : 0];
+    const int y = p / W, x = p - y * W;
+    const int gx = x + dx;
+    yk[k] = y;
+    colin[k] = k < nc && colw && gx >= 0 && gx < W;
+    const unsigned xc4 = 4u * (unsigned)clampi_s(gx, 0, W - 1);
+    const int tt = kp.extrapolate ? s_top[gx - xs0] : H;   // stage 5: rows above the top read the top
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int yc = clampi_s(y + dy0 + i, 0, H - 1);
+      w[k][i] = ldk(v4, (unsigned)v5_row(yc, tt, H, kp.ext_rows) * (4u * (unsigned)W) + xc4);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    int m = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int gy = yk[k] + dy0 + i;
+      m = max(m, (colin[k] && dy0 + i <= rl && gy >= 0 && gy < H) ? w[k][i] : 0);
+    }
+    m_out[k] = wave_max_nonneg(m);
+  }
+}
+
+// One workgroup per queued tile.  Its column records and tops give the
+// leading empty rows and the columns with holes; the hole rows are checked
+// cell by cell (all threads over the flattened list of hole-column rows).
+// Up to kFillSparse cells then each take the window max (window_max, one
+// wave per cell); a tile with more fills its bands that hold such cells
+// separably (fill_region).
+__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fill_tiles(FrameSource src, KParams kp, int lth) {
+  constexpr int SR = kBandRows + 2 * kFillRad;
+  __shared__ int S[SR * kDW];
+  __shared__ int s_top[kDW];
+  __shared__ int s_list[kFillSparse];
+  __shared__ short s_hcol[kLocalTW], s_hfirst[kLocalTW];
+  __shared__ int s_n, s_lead, s_nh, s_cand;
+  __shared__ unsigned s_bands;
+  const int tid = threadIdx.x, lane = tid & (kLanes - 1), wv = tid / kLanes;
+  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int gcap = src.plan ? src.plan->slow_cap : src.slow_cap;
+  const int lcap = src.plan ? src.plan->ltiles : src.single_ltiles;
+  const int count = min(slow[4], lcap);
+  const int32_t* queue = slow + fill_queue_offset(gcap);
+  const int kthr = key(kp.thr);
+  const int rl = kp.rl;
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const int t = queue[2 * i], fidx = queue[2 * i + 1];
+    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
+    f = uniform_frame(f);
+    const int H = f.H, W = f.W;
+    const int lt = t - f.ltile0, tr = lt / f.lcols, tc = lt - tr * f.lcols;
+    const int y0 = tr * lth, x0 = tc * kLocalTW;
+    const int rows = min(lth, H - y0), cols = min(kLocalTW, W - x0);
+    gcint* v4 = gc(f.v4);
+    gint* v4w = gw(f.v4);
+    __syncthreads();                                   // LDS of the previous tile is no longer read
+    if (tid == 0) {
+      s_n = 0;
+      s_lead = 0;
+      s_nh = 0;
+      s_cand = 0;
+      s_bands = 0u;
+    }
+    // tops of the columns x0 - rl .. x0 - rl + kDW - 1 (clamped into the image)
+    if (tid < kDW) s_top[tid] = kp.extrapolate ? gc(f.top)[clampi_s(x0 - rl + tid, 0, W - 1)] : H;
+    const int x = x0 + tid;
+    const int rec = tid < cols ? gc(f.v6p)[(size_t)tr * W + x] : 0;
+    __syncthreads();
+    // this thread's column: its leading rows y0 .. y0 + lead - 1, and
+    // whether empty rows follow its first non-empty row
+    int lead = 0;
+    if (tid < cols) {
+      const int top = s_top[tid + rl];
+      const int first = rec & 0xffff;
+      if ((top >= H || top < y0) && first != 0) lead = first == kRecNone ? rows : first;
+      unsigned bm = 0u;
+      if (lead > 0) {
+        bm |= band_bits(0, lead - 1);
+        atomicAdd(&s_lead, lead);
+      }
+      if (((unsigned)rec >> 16) == kRecHole && first + 1 < rows) {
+        bm |= band_bits(first + 1, rows - 1);
+        const int k = atomicAdd(&s_nh, 1);
+        s_hcol[k] = (short)tid;
+        s_hfirst[k] = (short)first;
+        atomicAdd(&s_cand, rows - 1 - first);
+      }
+      if (bm) atomicOr(&s_bands, bm);
     }
     __syncthreads();
-    // stage-5 values; cells outside the image are 0, which no max selects
-    // over a non-empty value
-#pragma unroll 8
-    for (int idx = tid; idx < sr * kDW; idx += kDenseThreads) {
-      const int rr = idx / kDW, cc = idx - rr * kDW;
-      const int gx = tx0 - rl + cc, gy = y0 - rl + rr;
-      const int x = clampi_s(gx, 0, W - 1), y = clampi_s(gy, 0, H - 1);
-      const int tt = s_top[cc];
-      const int v = v4[(size_t)v5_row(y, tt, H, kp.ext_rows) * W + x];
-      S[idx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? v : 0;
-    }
-    __syncthreads();
-    // horizontal window maxima of the 128 (>= 120) quarter columns, written
-    // over the staged values once every row has been read
-    {
-      const int rr = tid >> 2, j0 = (tid & 3) * 32;
-      const bool act = rr < sr;
-      int o[32];
-      if (act) {
-        if (rl == kFillRad) {
-          int a[62];
-#pragma unroll
-          for (int c = 0; c < 62; ++c) a[c] = S[rr * kDW + j0 + c];
-          vhgw31(a, o);
-        } else {
-#pragma unroll
-          for (int c = 0; c < 32; ++c) {
-            const int* p = S + rr * kDW + j0 + c;
-            int m = p[0];
-            for (int d = 1; d <= 2 * rl; ++d) m = max(m, p[d]);
-            o[c] = m;
-          }
+    bool dense = s_lead > kFillSparse || s_lead + s_cand > kFillScan;
+    if (!dense) {
+      for (int k = 0; k < lead; ++k) {
+        const int j = atomicAdd(&s_n, 1);
+        if (j < kFillSparse) s_list[j] = (y0 + k) * W + x;
+      }
+      // hole rows: the rows of every hole column, flattened over the threads
+      const int nh = s_nh;
+#pragma unroll 4
+      for (int idx = tid; idx < nh * rows; idx += kDenseThreads) {
+        const int k = idx / rows, r = idx - k * rows;
+        const int c = s_hcol[k];
+        const int y = y0 + r, xx = x0 + c;
+        const int v = v4[(size_t)y * W + xx];
+        if (r > s_hfirst[k] && v <= kthr) {
+          const int j = atomicAdd(&s_n, 1);
+          if (j < kFillSparse) s_list[j] = y * W + xx;
         }
       }
       __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < 32; ++c) S[rr * kDW + j0 + c] = o[c];
-      }
+      dense = s_n > kFillSparse;
     }
-    __syncthreads();
-    // vertical max at the empty cells of the quarter's own rows, one column
-    // per thread.  Output row r takes rows r .. r + 2 rl; when 2 rl >= QR - 2
-    // they split into rows r .. QR - 2 (a suffix maximum), QR - 1 .. 2 rl
-    // (shared by every row) and 2 rl + 1 .. 2 rl + r (a prefix maximum).
-    for (int c = tid; c < kGlobalTW; c += kDenseThreads) {
-      const int gx = tx0 + c;
-      if (gx >= W) continue;
-      const int tt = s_top[c + rl];
-      if (2 * rl >= QR - 2) {
-        int mid = 0;
-        for (int d = QR - 1; d <= 2 * rl; ++d) mid = max(mid, S[d * kDW + c]);
-        int lo[QR], hi[QR];
-        int acc = 0;
-        lo[QR - 1] = 0;
+    if (!dense) {
+      // three cells per wave at a time
+      constexpr int NC = 3;
+      const int n = s_n;
+      for (int j0 = wv * NC; j0 < n; j0 += NC * (kDenseThreads / kLanes)) {
+        const int nc = min(NC, n - j0);
+        int pos[NC], m[NC];
 #pragma unroll
-        for (int r = QR - 2; r >= 0; --r) {
-          acc = max(acc, S[r * kDW + c]);
-          lo[r] = acc;
-        }
-        acc = 0;
-        hi[0] = 0;
+        for (int k = 0; k < NC; ++k) pos[k] = uni(s_list[k < nc ? j0 + k : j0]);
+        window_max_n<NC>(f, kp, pos, nc, s_top, x0 - rl, lane, m);
+        if (lane == 0) {
 #pragma unroll
-        for (int r = 1; r < QR; ++r) {
-          acc = max(acc, S[(2 * rl + r) * kDW + c]);
-          hi[r] = acc;
+          for (int k = 0; k < NC; ++k)
+            if (k < nc && m[k] > 0) v4w[pos[k]] = m[k] | kFillTag;
         }
-#pragma unroll
-        for (int r = 0; r < QR; ++r) {
-          const int gy = y0 + r;
-          if (gy >= H) break;
-          const int v = v4[(size_t)v5_row(gy, tt, H, kp.ext_rows) * W + gx];
-          if (v <= kthr) v6p[(size_t)gy * W + gx] = max(max(mid, lo[r]), hi[r]);
-        }
-      } else {
-        for (int r = 0; r < QR && y0 + r < H; ++r) {
-          const int gy = y0 + r;
-          const int v = v4[(size_t)v5_row(gy, tt, H, kp.ext_rows) * W + gx];
-          if (v > kthr) continue;
-          int m = 0;
-          for (int d = 0; d <= 2 * rl; ++d) m = max(m, S[(r + d) * kDW + c]);
-          v6p[(size_t)gy * W + gx] = m;
-        }
+      }
+    } else {
+      const unsigned bands = s_bands;
+      for (int b = 0; b * kBandRows < rows; ++b) {
+        if (((bands >> b) & 1u) == 0u) continue;
+        const int by0 = y0 + b * kBandRows;
+        fill_region<kBandRows>(f, kp, by0, min(kBandRows, y0 + rows - by0), x0, cols, S, s_top, tid,
+                               [&](int y, int xx, int m) {
+                                 if (m > 0) v4w[(size_t)y * W + xx] = m | kFillTag;
+                               });
       }
     }
   }
@@ -958,8 +1282,8 @@ hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int ti
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
-  const bool fast = fast_chain(kp);
+hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, bool fast, int grid,
+                                hipStream_t s) {
 #define IPB_GS(TH)                                                                                     \
   if (fast) hipLaunchKernelGGL((k_global_stream<TH, true>), dim3(grid), dim3(kLanes), 0, s, src, kp); \
   else hipLaunchKernelGGL((k_global_stream<TH, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
@@ -985,18 +1309,36 @@ hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int t
   else return hipErrorInvalidValue;
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const bool fast = fast_chain(kp);
-#define IPB_GP(TH)                                                                                      \
-  if (fast) hipLaunchKernelGGL((k_global_patched<TH, true>), dim3(grid), dim3(kLanes), 0, s, src, kp); \
-  else hipLaunchKernelGGL((k_global_patched<TH, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  if (tile_id == 5) { IPB_GP(64) }
-  else if (tile_id == 6) { IPB_GP(32) }
-  else { IPB_GP(128) }
-#undef IPB_GP
+  if (tile_id == 5) hipLaunchKernelGGL((k_global_patched<64, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 6) hipLaunchKernelGGL((k_global_patched<32, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else hipLaunchKernelGGL((k_global_patched<128, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   return hipGetLastError();
 }
 
-int stream_resident_blocks(int phase, int tile_id, const KParams& kp) {
+hipError_t launch_prefill(const FrameSource& src, const KParams& kp, int local_rows, int scan_grid, int tile_grid,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_scan, dim3(scan_grid), dim3(kLanes), 0, s, src, kp, local_rows);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fill_tiles, dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
+  return hipGetLastError();
+}
+
+int prefill_resident_blocks() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles, kDenseThreads, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+// The default chain (5x5 median, 5x5 Gaussian, every stage, the full
+// extension): the phase-2 kernel's FAST variant.  The host takes it only
+// with the streaming phase 1, whose column records the fill ahead of phase 2
+// reads.
+bool fast_chain(const KParams& kp) {
+  return kp.rm == 2 && kp.rg == 2 && kp.last_stage == 9 && kp.blur == 0 && kp.ext_rows == 0;
+}
+
+int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast) {
   if (phase == 1) {
 #define X(S, R, ID) \
   if (kp.shape == S && kp.rd == R && tile_id == ID) return occupancy_s(k_local_stream<S, R, stream_local_rows(ID)>);
@@ -1004,7 +1346,6 @@ int stream_resident_blocks(int phase, int tile_id, const KParams& kp) {
 #undef X
     return 1;
   }
-  const bool fast = fast_chain(kp);
   if (tile_id == 5) return fast ? occupancy_s(k_global_stream<64, true>) : occupancy_s(k_global_stream<64, false>);
   if (tile_id == 6) return fast ? occupancy_s(k_global_stream<32, true>) : occupancy_s(k_global_stream<32, false>);
   if (tile_id == 7) return fast ? occupancy_s(k_global_stream<128, true>) : occupancy_s(k_global_stream<128, false>);

@@ -219,6 +219,36 @@ def test_special_values():
     assert_all_stages(m, tag="specials")
 
 
+def fill_case_map(seed):
+    """A dense random map with regions emptied so that the 31x31 fill meets
+    every case: columns without a top, holes below a column's top that span
+    tile rows, a small gap, and empty rows above a top (the extension's)."""
+    rng = np.random.default_rng(seed)
+    m = synth.random_map(rng, 300, 760, 0.3, 1.0, 80.0)
+    m[:, 100:150] = 0.0            # columns without any value
+    m[90:260, 300:420] = 0.0       # a large hole across tile rows
+    m[60:72, 500:530] = 0.0        # a small gap across the 64-row tile boundary
+    m[6:140, 600:700] = 0.0        # below the top rows 0-5: holes; further right: empty rows above the top
+    m[0:6, 650:700] = 0.0
+    return m
+
+
+@pytest.mark.parametrize("tl", [0, 5, 6, 7])
+def test_fill_ahead_of_phase2_cases(tl):
+    """The default chain fills the cells empty after stage 5 ahead of phase 2
+    (per cell for a few, per band separably for many): bit-exact."""
+    p = api.Params(tile_local=tl)
+    for seed in (21, 22):
+        m = fill_case_map(seed)
+        want = oracle.complete(m, oracle_params(p))[8]
+        assert_stage_equal(gpu_stage(m, 9, p), want, f"fill cases tl={tl} seed={seed}")
+    ts = [torch.from_numpy(fill_case_map(s)).to(DEV) for s in (23, 24)]
+    outs = api.complete_batch(ts, p)
+    for t, o in zip(ts, outs):
+        want = oracle.complete(t.cpu().numpy(), oracle_params(p))[8]
+        assert_stage_equal(o.cpu().numpy(), want, f"fill cases batch tl={tl}")
+
+
 def test_alloc_path_and_in_place():
     f = synth.lidar_frame(200, 333, seed=[14], n_rows=48, density=0.05)
     t = torch.from_numpy(f.sparse).to(DEV)
