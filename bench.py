@@ -171,11 +171,31 @@ class Batches:
                      "ipb_complete_planned")
 
     def time_planned(self, steps, warmup):
-        """Mean ms per batch and per launch step, HIP events on the launch stream."""
+        """Mean ms per batch over `steps` timed steps, and the dominant
+        kernel's mean duration from HIP events around it on the launch stream
+        in the same timed steps (two events per step; the other launch steps
+        run between them unbracketed).  Per-step durations of every launch
+        step come from a separate, untimed pass with events between all steps
+        (those events add a few microseconds per step)."""
         torch = self.torch
         for i in range(warmup):
             self.run_phase(self.sets[i % len(self.sets)], -1)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(steps)]
+        # untimed pass: every launch step bracketed
+        diag = max(5, min(steps, 50))
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(diag)]
+        torch.cuda.synchronize()
+        for i in range(diag):
+            st = self.sets[i % len(self.sets)]
+            for ph in range(len(PHASES)):
+                evs[i][ph].record(self.stream)
+                self.run_phase(st, ph)
+            evs[i][len(PHASES)].record(self.stream)
+        torch.cuda.synchronize()
+        k_ms = {name: sum(e[k].elapsed_time(e[k + 1]) for e in evs) / diag for k, name in enumerate(PHASES)}
+        dom = max(BYTES_PER_PX, key=lambda k: k_ms[k])
+        dph = PHASES.index(dom)
+        # timed pass
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
@@ -183,14 +203,17 @@ class Batches:
         for i in range(steps):
             st = self.sets[i % len(self.sets)]
             for ph in range(len(PHASES)):
-                evs[i][ph].record(self.stream)
-                self.run_phase(st, ph)
-            evs[i][len(PHASES)].record(self.stream)
+                if ph == dph:
+                    ev[i][0].record(self.stream)
+                    self.run_phase(st, ph)
+                    ev[i][1].record(self.stream)
+                else:
+                    self.run_phase(st, ph)
         t1.record(self.stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        k_ms = {name: sum(e[k].elapsed_time(e[k + 1]) for e in evs) / steps for k, name in enumerate(PHASES)}
-        return t0.elapsed_time(t1) / steps, k_ms, wall
+        dom_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+        return t0.elapsed_time(t1) / steps, k_ms, (dom, dom_ms), wall
 
     def time_graph(self, steps, warmup):
         """Mean ms per batch through GraphBatch (plan rewrite + one graph replay)."""
@@ -238,11 +261,12 @@ class Batches:
         return a.elapsed_time(b) / reps
 
 
-def roofline(k_ms, px, workload):
-    dom = max(BYTES_PER_PX, key=lambda k: k_ms[k])
-    achieved = BYTES_PER_PX[dom] * px / (k_ms[dom] / 1e3) / 1e9
+def roofline(dom_timed, px, workload):
+    dom, ms = dom_timed
+    achieved = BYTES_PER_PX[dom] * px / (ms / 1e3) / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom, workload)}
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dom, workload),
+            "launch_ms": round(ms, 5), "bytes_per_launch": BYTES_PER_PX[dom] * px}
 
 
 def record(args, workload, value, unit, ms_step, extra, higher=True):
@@ -277,14 +301,15 @@ def bench_batch(args, workload, cpu, serve_host=None):
                                                for r in report]}
         del probe
     b = Batches(maps, params)
-    ms_step, k_ms, wall = b.time_planned(args.steps, args.warmup)
+    ms_step, k_ms, dom_timed, wall = b.time_planned(args.steps, args.warmup)
     fps = b.n / (ms_step / 1e3)
     extra.update({
         "config": None,
-        "roofline": roofline(k_ms, b.px, workload),
+        "roofline": roofline(dom_timed, b.px, workload),
         "cpu_baseline": cpu,
         "hbm_gbps_algorithmic_pipeline": round(16 * b.px / (ms_step / 1e3) / 1e9, 1),
         "kernel_ms": {k: round(v, 5) for k, v in k_ms.items()},
+        "kernel_ms_note": "untimed pass with HIP events between every launch step",
         "wall_s": round(wall, 3),
     })
     g_ms, replays = b.time_graph(max(10, args.steps // 2), 4)
