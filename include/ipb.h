@@ -174,7 +174,7 @@ int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p,
  *   0 reset the column tables and the tile queues;
  *   1 stages 1-4;
  *   2 the default chain (Sec. III; Tables 2 and 3: 5x5 median, 5x5
- *     Gaussian, the full extension) on the streaming kernels: the 31x31
+ *     binomial Gaussian, the full extension) on the streaming kernels: the 31x31
  *     fill of the cells that are empty after stage 5, written into the
  *     stage-4 map ahead of phase 2 (no-op otherwise);
  *   3 stages 5-9 (other chains on the streaming kernel: every tile,

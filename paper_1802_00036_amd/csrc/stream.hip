@@ -404,7 +404,7 @@ __device__ __forceinline__ double hsum5(double wc, double w1, double w2, int m2,
 // their stage-6 value from f.v6p (written by k_fill_cells / k_fill_dense).
 // s_cells: LDS lists of the first kCellEmpty empty cells of each quarter
 // (first pass only).
-template <int TH, bool PATCHED, bool FAST>
+template <int TH, bool PATCHED, bool FAST, bool INTERIOR = false>
 __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int fidx, int gt,
                                                    int ty0, int tx0, int lane, int32_t* slow, int cap, int* s_cells) {
   const int H = f.H, W = f.W;
@@ -466,7 +466,9 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
     selb = (sb & 1) != 0;
   }
 
-  const double wc = kp.gw[0], w1 = kp.gw[1], w2 = kp.gw[2], gsc = kp.gscale;
+  // FAST: the binomial taps (1 4 6 4 1)/16 as constants
+  const double wc = FAST ? 6.0 : kp.gw[0], w1 = FAST ? 4.0 : kp.gw[1], w2 = FAST ? 1.0 : kp.gw[2];
+  const double gsc = FAST ? 1.0 / 256.0 : kp.gscale;
   const int q0 = ty0 - 4;
   const int n = TH + 8;
   int raw[8][2];         // stage-5 keys (window of the median)
@@ -617,7 +619,8 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
       hs[u][0] = hsum5(wc, w1, w2, La, Lb, v7a, v7b, Ra);
       hs[u][1] = hsum5(wc, w1, w2, Lb, v7a, v7b, Ra, Rb);
     }
-    if (m == 2 && q0 + 2 <= 0) {                // rows -1, -2 mirror rows 1, 2
+    if (INTERIOR) {                             // no border row among the tile's rows
+    } else if (m == 2 && q0 + 2 <= 0) {         // rows -1, -2 mirror rows 1, 2
       hs[(u - 3) & 7][0] = hs[(u - 1) & 7][0];
       hs[(u - 3) & 7][1] = hs[(u - 1) & 7][1];
       hs[(u - 4) & 7][0] = hs[u][0];
@@ -633,7 +636,7 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
 
     // Stages 8 and 9 for row g = q - 4.
     const int g = q - 4;
-    if (FAST ? g < H : (g >= ty0 && g < ty0 + TH && g < H && last >= 8)) {
+    if (FAST ? (INTERIOR || g < H) : (g >= ty0 && g < ty0 + TH && g < H && last >= 8)) {
       const int ca7 = s7[(u - 2) & 7][0], cb7 = s7[(u - 2) & 7][1];
       const bool ma = ca7 > kthr, mb = cb7 > kthr;
       float oa, ob;
@@ -742,8 +745,13 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) voi
     f = uniform_frame(f);
     const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
-    global_stream_tile<TH, false, FAST>(f, kp, t, fidx, gt, tr * TH, (gt - tr * f.gcols) * kGlobalTW, lane, slow,
-                                        cap, s_cells);
+    const int ty0 = tr * TH, tx0 = (gt - tr * f.gcols) * kGlobalTW;
+    // FAST tiles whose rows all lie away from the frame's first and last two
+    // rows take a variant without the Gaussian's border rows
+    if (FAST && ty0 >= 4 && ty0 + TH + 2 <= f.H)
+      global_stream_tile<TH, false, FAST, FAST>(f, kp, t, fidx, gt, ty0, tx0, lane, slow, cap, s_cells);
+    else
+      global_stream_tile<TH, false, FAST, false>(f, kp, t, fidx, gt, ty0, tx0, lane, slow, cap, s_cells);
   }
 }
 
@@ -1330,12 +1338,13 @@ int prefill_resident_blocks() {
   return nb > 0 ? nb : 1;
 }
 
-// The default chain (5x5 median, 5x5 Gaussian, every stage, the full
-// extension): the phase-2 kernel's FAST variant.  The host takes it only
+// The default chain (5x5 median, the binomial 5x5 Gaussian, every stage, the
+// full extension): the phase-2 kernel's FAST variant.  The host takes it only
 // with the streaming phase 1, whose column records the fill ahead of phase 2
 // reads.
 bool fast_chain(const KParams& kp) {
-  return kp.rm == 2 && kp.rg == 2 && kp.last_stage == 9 && kp.blur == 0 && kp.ext_rows == 0;
+  return kp.rm == 2 && kp.rg == 2 && kp.last_stage == 9 && kp.blur == 0 && kp.ext_rows == 0 && kp.gw[0] == 6.0 &&
+         kp.gw[1] == 4.0 && kp.gw[2] == 1.0 && kp.gscale == 1.0 / 256.0;
 }
 
 int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast) {
