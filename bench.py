@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "frames/s and HBM GB/s at 375x1242 batched; p50/p99 latency under serving load"
 HBM_PEAK_GBPS = 8000.0
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # non-packed 32-bit VALU lane-operations
 # launch steps of one batch (ipb_complete_planned phases 0..5) and the kernels each launches
 PHASES = ["k_reset", "k_local_stream", "k_fill_scan+k_fill_tiles", "k_global_stream",
           "k_fill_cells+k_fill_dense+k_global_patched", "k_global_slow"]
@@ -116,9 +117,9 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source and this workload."""
+def profile_for(kernel: str, workload: str):
+    """The kernel's entry in the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source and this workload."""
     if workload != "c2":
         return None
     try:
@@ -128,8 +129,28 @@ def traffic_for(kernel: str, workload: str):
         return None
     if t.get("kernel_sha") != kernel_sha():
         return None
-    k = t.get("kernels", {}).get(kernel)
+    return t.get("kernels", {}).get(kernel)
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled) or None."""
+    k = profile_for(kernel, workload)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def valu_ceiling(kernel: str, workload: str, ms: float):
+    """The kernel against the vector-ALU issue ceiling: lane-operations per
+    launch (SQ_INSTS_VALU x 64 from the committed counter summary) over the
+    launch duration measured here, against 256 CUs x 4 SIMD16 x 16 lanes x
+    2.4 GHz = 39.3 T lane-ops/s (a wave64 instruction takes 4 cycles)."""
+    k = profile_for(kernel, workload)
+    if k is None or not k.get("valu_instr_per_launch"):
+        return None
+    ops = 64 * k["valu_instr_per_launch"]
+    achieved = ops / (ms / 1e3) / 1e12
+    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 2), "peak": VALU_PEAK_TOPS,
+            "unit": "T lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "lane_ops_per_launch": ops,
+            "source": "SQ_INSTS_VALU from the committed counter summary, duration from this run"}
 
 
 class Batches:
@@ -306,6 +327,7 @@ def bench_batch(args, workload, cpu, serve_host=None):
     extra.update({
         "config": None,
         "roofline": roofline(dom_timed, b.px, workload),
+        "valu_ceiling": valu_ceiling(dom_timed[0], workload, dom_timed[1]),
         "cpu_baseline": cpu,
         "hbm_gbps_algorithmic_pipeline": round(16 * b.px / (ms_step / 1e3) / 1e9, 1),
         "kernel_ms": {k: round(v, 5) for k, v in k_ms.items()},
