@@ -338,7 +338,7 @@ size_t frame_ws_bytes(int H, int W, const Resolved& r) {
 // them): 0 reset, 1 stages 1-4, 2 the fill of stage 6 ahead of phase 2,
 // 3 stages 5-9, 4 the second pass of queued quarters, 5 tiny frames.
 int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last_stage, int max_lt, int max_gt,
-                  int max_cols, bool persistent, hipStream_t s) {
+                  int max_cols, bool persistent, bool may_tiny, hipStream_t s) {
   int dev = 0;
   int st = device_cus(&dev);
   if (st != IPB_OK) return st;
@@ -388,7 +388,8 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
     e = launch_global_repair(src, kp, r.gtile, rgrid, cgrid, s);
     if (e != hipSuccess) return hip_fail(e);
   }
-  if ((phase == -1 || phase == 5) && r.gstream) {
+  // (skipped when the caller knows no frame has under 3 rows or columns)
+  if ((phase == -1 || phase == 5) && r.gstream && may_tiny) {
     const int per = slow_subtiles(r.gth, r.gtw);
     // frames under 3 rows or columns are rare and small: one workgroup per CU
     const int sgrid = std::max(1, std::min(max_gt * per, cus));
@@ -419,7 +420,21 @@ int run_single(const float* in, int H, int W, const ipb_params* p, float* out, i
     r.ltw = local_tile_cols(1);
   }
   FrameSource src = single_source(in, H, W, out, ws, r);
-  return launch_phases(src, r, -1, last_stage, src.single_ltiles, src.single_gtiles, W, false, s);
+  return launch_phases(src, r, -1, last_stage, src.single_ltiles, src.single_gtiles, W, false, H < 3 || W < 3, s);
+}
+
+int planned(const void* plan_dev, const ipb_params* p, int phase, int max_tiles_local, int max_tiles_global,
+            int max_cols, bool may_tiny, void* stream) {
+  Resolved r;
+  int st = resolve(p, &r);
+  if (st != IPB_OK) return st;
+  if (plan_dev == nullptr || phase < -1 || phase > 5) return IPB_ERR_INVALID_ARG;
+  if (max_tiles_local < 1 || max_tiles_global < 1 || max_cols < 1) return IPB_ERR_INVALID_ARG;
+  FrameSource src;
+  std::memset(&src, 0, sizeof(src));
+  src.plan = static_cast<const PlanHeader*>(plan_dev);
+  return launch_phases(src, r, phase, 9, max_tiles_local, max_tiles_global, max_cols, true, may_tiny,
+                       static_cast<hipStream_t>(stream));
 }
 
 }  // namespace
@@ -524,18 +539,11 @@ int ipb_plan_totals(const void* plan_host, int* n, int* tiles_local, int* tiles_
   return IPB_OK;
 }
 
+
 int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase, int max_tiles_local,
                          int max_tiles_global, int max_cols, void* stream) {
-  Resolved r;
-  int st = resolve(p, &r);
-  if (st != IPB_OK) return st;
-  if (plan_dev == nullptr || phase < -1 || phase > 5) return IPB_ERR_INVALID_ARG;
-  if (max_tiles_local < 1 || max_tiles_global < 1 || max_cols < 1) return IPB_ERR_INVALID_ARG;
-  FrameSource src;
-  std::memset(&src, 0, sizeof(src));
-  src.plan = static_cast<const PlanHeader*>(plan_dev);
-  return launch_phases(src, r, phase, 9, max_tiles_local, max_tiles_global, max_cols, true,
-                       static_cast<hipStream_t>(stream));
+  // a plan may be rewritten for other frames after the launch is captured
+  return planned(plan_dev, p, phase, max_tiles_local, max_tiles_global, max_cols, true, stream);
 }
 
 int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p, void* ws, size_t ws_bytes,
@@ -588,7 +596,9 @@ int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p, void
   e = hipEventRecord(slot.ev, s);
   if (e != hipSuccess) return hip_fail(e);
   slot.pending = true;
-  return ipb_complete_planned(ws, p, -1, lt, gt, cols, stream);
+  bool tiny = false;
+  for (int i = 0; i < n; ++i) tiny = tiny || frames[i].H < 3 || frames[i].W < 3;
+  return planned(ws, p, -1, lt, gt, cols, tiny, stream);
 }
 
 const char* ipb_status_string(int status) {

@@ -134,3 +134,52 @@ def test_quality_sweep_runs_every_design_step():
     assert np.isclose(rows[-1]["rmse_mm"], quality.pooled(
         [api.complete(torch.from_numpy(fr.sparse).to(DEV)).cpu().numpy() for fr in frames],
         [fr.dense_gt for fr in frames])["rmse_mm"], rtol=1e-3)
+
+
+def _planned_steps(frames, outs, p):
+    """The bench's launch configuration: one plan for the whole batch, then
+    ipb_complete_planned one launch step at a time (steps 0-5)."""
+    import ctypes
+    from paper_1802_00036_amd import _lib as L
+    lib = L.lib()
+    cp = p.to_c()
+    arr = api.frames_array(frames, outs)
+    nb = int(lib.ipb_batch_workspace_bytes(arr, len(frames), ctypes.byref(cp)))
+    ws = api._workspace(nb, frames[0].device)
+    pb = int(lib.ipb_batch_plan_bytes(len(frames)))
+    ph = ctypes.create_string_buffer(pb)
+    L.check(lib.ipb_batch_plan(arr, len(frames), ctypes.byref(cp), ctypes.c_void_p(ws.data_ptr()), nb, ph, pb),
+            "ipb_batch_plan")
+    n, lt, gt, cols = (ctypes.c_int() for _ in range(4))
+    lib.ipb_plan_totals(ph, ctypes.byref(n), ctypes.byref(lt), ctypes.byref(gt), ctypes.byref(cols))
+    pd = torch.frombuffer(bytearray(ph.raw), dtype=torch.uint8).to(frames[0].device)
+    sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for step in range(6):
+        L.check(lib.ipb_complete_planned(ctypes.c_void_p(pd.data_ptr()), ctypes.byref(cp), step, lt.value, gt.value,
+                                         cols.value, sh), "ipb_complete_planned")
+    torch.cuda.synchronize()
+    del ws, pd
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_bench_configuration_full_batch(cfg):
+    """The whole batch the bench times (64 x 375x1242; 16 x 1024x4096 with the
+    tiles the autotuner picks for it), in the bench's launch configuration:
+    every frame bitwise equal to the frame completed alone, and frames spread
+    over the batch equal to the oracle."""
+    p = api.Params(max_depth=140.0) if cfg == 4 else api.Params()
+    if cfg == 4:
+        p = dataclasses.replace(p, tile_local=5, tile_global=5)
+    fr = synth.config_frames(cfg)
+    frames = [torch.from_numpy(f.sparse).to(DEV) for f in fr]
+    outs = [torch.empty_like(t) for t in frames]
+    print(f"[bench config c{cfg}] {len(frames)} frames", flush=True)
+    _planned_steps(frames, outs, p)
+    for i, (t, o) in enumerate(zip(frames, outs)):
+        assert np.array_equal(bits(o), bits(api.complete(t, p))), f"c{cfg} frame {i}: batch != alone"
+    sample = [0, len(fr) // 2, len(fr) - 1] if cfg == 4 else [0, 9, 21, 33, 47, 63]
+    for i in sample:
+        want = oracle.complete_map(fr[i].sparse, oracle.Params(max_depth=p.max_depth))
+        got = np.ascontiguousarray(outs[i].cpu().numpy())
+        assert np.array_equal(got.view(np.uint32), np.ascontiguousarray(want, np.float32).view(np.uint32)), \
+            f"c{cfg} frame {i} differs from the oracle"
