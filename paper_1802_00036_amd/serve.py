@@ -308,11 +308,17 @@ class GraphExecutor(Executor):
     default priority.  Per slot and bucket there is one GraphBatch per
     capacity tier (e.g. 1, 4 and 16 frames): a batch runs on the smallest
     tier that holds it, so a lone request under light load does not pay for
-    the launch grid of a full batch."""
+    the launch grid of a full batch.  With `direct_single`, a lone request
+    skips the graph (and its plan copy) and goes straight to ipb_complete_ws
+    on the slot's stream, with a workspace resident per slot."""
 
     def __init__(self, slots: int = 2, max_batch: int = 16, device=None, default_params=None,
-                 tiers: Optional[Sequence[int]] = None):
+                 tiers: Optional[Sequence[int]] = None, direct_single: bool = True):
         from .api import Params
+        self.direct_single = direct_single
+        self.ws: Dict[int, object] = {}
+        self.ws_bytes: Dict[int, int] = {}
+        self.cparams: Dict[Hashable, object] = {}
         self.slots = slots
         self.max_batch = max_batch
         if tiers is None:
@@ -351,7 +357,33 @@ class GraphExecutor(Executor):
                     for _ in range(3):
                         eng.run([x]).synchronize()
 
+    def _direct(self, slot: int, r: Request):
+        import ctypes
+        from . import _lib as L
+        from .api import _workspace
+        lib = L.lib()
+        stream = self.streams[slot]
+        key = _params_key(r.params)
+        cp = self.cparams.get(key)
+        if cp is None:
+            cp = self.cparams[key] = (r.params or self.default_params).to_c()
+        H, W = r.shape
+        need = int(lib.ipb_workspace_bytes(H, W, ctypes.byref(cp)))
+        if need > self.ws_bytes.get(slot, 0):
+            with torch.cuda.stream(stream):
+                self.ws[slot] = _workspace(need, self.device)
+            self.ws_bytes[slot] = need
+        o = self.pool.get(r.shape)
+        L.check(lib.ipb_complete_ws(ctypes.c_void_p(r.frame.data_ptr()), H, W, ctypes.byref(cp),
+                                    ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(self.ws[slot].data_ptr()),
+                                    self.ws_bytes[slot], ctypes.c_void_p(stream.cuda_stream)), "ipb_complete_ws")
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        return ev, [o]
+
     def launch(self, slot: int, bucket: Hashable, reqs: Sequence[Request]):
+        if self.direct_single and len(reqs) == 1:
+            return self._direct(slot, reqs[0])
         eng = self._engine(slot, bucket, reqs[0].params, len(reqs))
         outs = [self.pool.get(r.shape) for r in reqs]
         ev = eng.run([r.frame for r in reqs], outs)

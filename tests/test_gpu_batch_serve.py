@@ -89,7 +89,7 @@ def test_autotune_picks_a_valid_pair_and_results_do_not_change(tmp_path, monkeyp
         assert np.array_equal(bits(o), bits(api.complete(f)))
 
 
-@pytest.mark.parametrize("executor", ["graph", "per_frame"])
+@pytest.mark.parametrize("executor", ["graph", "graph_only", "per_frame"])
 def test_served_results_equal_alone(executor):
     rng = np.random.default_rng(23)
     shapes = [(352, 1216), (375, 1242), (200, 640), (96, 333)]
@@ -99,11 +99,12 @@ def test_served_results_equal_alone(executor):
         H, W = shapes[int(rng.integers(len(shapes)))]
         frames.append(lidar(H, W, [23, i], density=float(rng.uniform(0.02, 0.1))))
         params.append(p140 if i % 5 == 0 else None)
-    if executor == "graph":
-        ex = serve.GraphExecutor(slots=3, max_batch=4)
+    if executor.startswith("graph"):
+        # "graph": lone requests go straight to ipb_complete_ws; "graph_only": every batch replays a graph
+        ex = serve.GraphExecutor(slots=3, max_batch=4, direct_single=executor == "graph")
     else:
         ex = serve.PerFrameExecutor()
-    srv = serve.Server(ex, mem_budget=256 << 20, max_batch=4 if executor == "graph" else 1)
+    srv = serve.Server(ex, mem_budget=256 << 20, max_batch=4 if executor.startswith("graph") else 1)
     arrivals = np.cumsum(rng.exponential(1 / 4000.0, len(frames)))
     stats = serve.run_trace(srv, frames, arrivals, params)
     torch.cuda.synchronize()
@@ -114,7 +115,7 @@ def test_served_results_equal_alone(executor):
         alone = api.complete(f, params[i] or api.Params())
         torch.cuda.synchronize()
         assert np.array_equal(bits(by_id[i].out), bits(alone)), f"request {i}"
-    if executor == "graph":
+    if executor.startswith("graph"):
         assert ex.tiers == [1, 4]
         assert {len(eng.capacity) for eng in ex.engines.values()} <= {1, 4}
 
