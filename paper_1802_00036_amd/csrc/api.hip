@@ -367,8 +367,8 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
   if (last_stage < 5) return IPB_OK;
   if ((phase == -1 || phase == 2) && prefill) {
     // one scanning wave per phase-1 tile (those of the first tile row work);
-    // one workgroup per queued tile, at most the resident ones
-    const int tgrid = std::max(1, std::min(max_lt, prefill_res(dev) * cus));
+    // one workgroup per queued band, at most the resident ones
+    const int tgrid = std::max(1, (int)std::min<long long>((long long)kBandsPerTile * max_lt, prefill_res(dev) * cus));
     e = launch_prefill(src, kp, r.lth, max_lt, tgrid, s);
     if (e != hipSuccess) return hip_fail(e);
   }

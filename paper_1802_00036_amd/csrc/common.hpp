@@ -109,20 +109,22 @@ struct FrameSource {
 //             (k_fill_cells): two ints, the frame index and y * W + x;
 //   slow[1]   tiles of frames under 3 rows or columns (launch tile ids),
 //             recomputed by the LDS kernel;
-//   slow[4]   phase-1 tiles holding a cell that is empty after the
-//             extension, for the fill ahead of phase 2 (k_fill_scan,
-//             k_fill_tiles): two ints, the launch tile id and the frame index;
+//   slow[4]   32-row bands of phase-1 tiles that may hold a cell empty
+//             after the extension, for the fill ahead of phase 2
+//             (k_fill_scan, k_fill_tiles): two ints, the launch tile id and
+//             the frame index with the band in bits 24..25;
 //   slow[8 ..)              the first queue (8 gcap ints), the dense queue
 //                           (8 gcap ints), the tiny-frame queue (gcap), the
 //                           cell queue (8 kCellEmpty gcap ints), then the
-//                           phase-1 tile queue (2 lcap ints).
+//                           band queue (2 kBandsPerTile lcap ints).
 // The first three queues and the cell queue serve the general phase 2 (its
 // second pass); the phase-1 tile queue serves the default chain, whose fill
 // runs before phase 2.
 constexpr int kCellEmpty = 32;
 constexpr int kQueueHead = 8;
+constexpr int kBandsPerTile = 4;   // 32-row bands of a phase-1 tile (at most 128 rows)
 __host__ __device__ inline size_t slow_queue_ints(int gcap, int lcap) {
-  return kQueueHead + (17 + 8 * kCellEmpty) * (size_t)gcap + 2 * (size_t)lcap;
+  return kQueueHead + (17 + 8 * kCellEmpty) * (size_t)gcap + 2 * kBandsPerTile * (size_t)lcap;
 }
 __host__ __device__ inline int sparse_queue_offset(int) { return kQueueHead; }
 __host__ __device__ inline int dense_queue_offset(int cap) { return kQueueHead + 8 * cap; }

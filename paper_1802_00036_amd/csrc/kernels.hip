@@ -41,18 +41,6 @@ __device__ __forceinline__ const FrameDesc* plan_frames(const PlanHeader* p) {
   return reinterpret_cast<const FrameDesc*>(p + 1);
 }
 
-template <bool LOCAL>
-__device__ __forceinline__ int find_frame(const PlanHeader* p, int t) {
-  const FrameDesc* f = plan_frames(p);
-  int lo = 0, hi = p->n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int start = LOCAL ? f[mid].ltile0 : f[mid].gtile0;
-    if (start <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Spread a rows x cols rectangle over the workgroup: each thread takes one
 // column and a run of consecutive rows (lanes of a wave hold neighbouring
 // columns of the same rows, so LDS reads are bank-conflict free and global
@@ -645,11 +633,18 @@ __global__ __launch_bounds__(kThreads) void k_reset(FrameSource src) {
   const int gid = blockIdx.x * kThreads + threadIdx.x, stride = gridDim.x * kThreads;
   if (blockIdx.x == 0 && threadIdx.x < kQueueHead && slow != nullptr) slow[threadIdx.x] = 0;
   for (int i = gid; i < n; i += stride) base[i] = kNoTop;
-  // the frame of every tile, so that a tile's wave finds its frame with one load
+  // the frame of every tile, so that a tile's wave finds its frame with one
+  // load: a workgroup per frame writes its tiles' entries
   if (src.plan) {
     const PlanHeader* p = src.plan;
-    for (int i = gid; i < p->ltiles; i += stride) p->ltab[i] = find_frame<true>(p, i);
-    for (int i = gid; i < p->gtiles; i += stride) p->gtab[i] = find_frame<false>(p, i);
+    const FrameDesc* fd = plan_frames(p);
+    for (int f = blockIdx.x; f < p->n; f += gridDim.x) {
+      const FrameDesc d = fd[f];
+      const int nl = d.lcols * ((d.H + p->lt_rows - 1) / p->lt_rows);
+      const int ng = d.gcols * ((d.H + p->gt_rows - 1) / p->gt_rows);
+      for (int j = threadIdx.x; j < nl; j += kThreads) p->ltab[d.ltile0 + j] = f;
+      for (int j = threadIdx.x; j < ng; j += kThreads) p->gtab[d.gtile0 + j] = f;
+    }
   }
 }
 

@@ -150,10 +150,9 @@ __device__ __forceinline__ void for_slots(F&& f) {
 }
 
 // Phase-1 column record of a tile column: the first non-empty row relative
-// to the tile's first row (low 16 bits; kRecNone: none) and whether an empty
-// row follows it in the tile (high 16 bits: kRecHole, else kRecNone).
+// to the tile's first row (low 16 bits; kRecNone: none) and the 32-row bands
+// of the tile that hold an empty row after it (high 16 bits, bit b: band b).
 constexpr int kRecNone = 0xffff;
-constexpr int kRecHole = 1;
 __device__ __forceinline__ unsigned short record_first(int first, int ty0) {
   return (unsigned short)(first == kNoTop ? kRecNone : first - ty0);
 }
@@ -208,8 +207,8 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   // half is set here to "none" and overwritten on the rare rows that hold a
   // hole; the first-row half is written at the end of the tile
   gchar* rec = (gchar*)(char*)f.v6p + 4 * (size_t)(ty0 / TH) * W;   // uniform row base; lanes add ua / ub
-  if (outa) st16(rec, ua + 2, kRecNone);
-  if (outb) st16(rec, ub + 2, kRecNone);
+  if (outa) st16(rec, ua + 2, 0);
+  if (outb) st16(rec, ub + 2, 0);
   gcfloat* in = gcf(f.in);
   const unsigned W4 = 4u * (unsigned)W;
   const unsigned sink = (unsigned)H * W4;                 // scratch slot past the stage-4 map
@@ -335,8 +334,10 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         const bool hole_a = o4row && outa && oa <= kthr && first_a < o4;
         const bool hole_b = o4row && outb && ob <= kthr && first_b < o4;
         if (__builtin_expect(__ballot(hole_a || hole_b) != 0, 0)) {
-          if (hole_a) st16(rec, ua + 2, kRecHole);
-          if (hole_b) st16(rec, ub + 2, kRecHole);
+          const unsigned bit = 1u << (16 + (o4 - ty0) / 32);
+          unsigned* rw = reinterpret_cast<unsigned*>(f.v6p) + (size_t)(ty0 / TH) * W;
+          if (hole_a) atomicOr(rw + ca, bit);
+          if (hole_b) atomicOr(rw + cb, bit);
         }
       }
       const unsigned ro = (unsigned)o4 * W4;
@@ -996,19 +997,39 @@ __global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, K
 // phase 2 reads stage-6 values with the tag cleared.  Every cell belongs to
 // one phase-1 tile, whose workgroup alone writes it.
 
-// Whether a tile column's record holds such a cell, given the
-// column's top (>= H: none) and the tile's first row.
-__device__ __forceinline__ bool record_needs_fill(int rec, int top, int y0, int H) {
+// bits of the bands (kBandRows rows) that rows lo .. hi of a tile touch
+constexpr int kBandRows = 32;
+__device__ __forceinline__ unsigned band_bits(int lo, int hi) {
+  return (2u << (hi / kBandRows)) - (1u << (lo / kBandRows));
+}
+
+// The bands of a tile column (rows: the tile's rows in the frame) that hold
+// such a cell, given its record, the column's top (>= H: none) and the
+// tile's first row: those of its leading rows, and those the record marks
+// as holding an empty row after its first non-empty row.
+__device__ __forceinline__ unsigned record_bands(int rec, int top, int y0, int rows, int H) {
   const int first = rec & 0xffff;
-  const bool lead = (top >= H || top < y0) && first != 0;
-  const bool hole = ((unsigned)rec >> 16) == kRecHole;
-  return lead || hole;
+  unsigned m = 0u;
+  if ((top >= H || top < y0) && first != 0) m |= band_bits(0, (first == kRecNone ? rows : first) - 1);
+  return m | (((unsigned)rec >> 16) & ((1u << kBandsPerTile) - 1u));
+}
+
+// Bitwise or over the wave, as a uniform value (as wave_max_nonneg).
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+  int x = (int)v;
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
+  return (unsigned)__builtin_amdgcn_readlane(x, 63);
 }
 
 // One wave per column of phase-1 tiles (the waves of the first tile row's
 // tiles) walks the records of every tile row, eight tile rows at a time, and
-// queues the tiles that hold such a cell: the launch tile id and the frame
-// index.  Frames under 3 rows or columns are left to phase 2, which
+// queues the 32-row bands of tiles that may hold such a cell: the launch
+// tile id, and the frame index with the band in bits 24..25.  Frames under 3 rows or columns are left to phase 2, which
 // recomputes them whole.
 __global__ __launch_bounds__(kLanes) void k_fill_scan(FrameSource src, KParams kp, int lth) {
   const int lane = threadIdx.x;
@@ -1039,32 +1060,33 @@ __global__ __launch_bounds__(kLanes) void k_fill_scan(FrameSource src, KParams k
         ra[k] = rec[row + xac];
         rb[k] = rec[row + xbc];
       }
-      unsigned need = 0u;
+      // bands with candidates: four bits per tile row (bit 4 k + b: tile row
+      // tr0 + k, band b), or-ed over the tile columns of the wave
+      unsigned m = 0u;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const int y0 = (tr0 + k) * lth;
-        const bool nd = (ina && record_needs_fill(ra[k], ta, y0, H)) || (inb && record_needs_fill(rb[k], tb, y0, H));
-        if (tr0 + k < ntr && __ballot(nd) != 0) need |= 1u << k;
+        const int y0 = (tr0 + k) * lth, rows = min(lth, H - y0);
+        if (tr0 + k < ntr) {
+          const unsigned mk = (ina ? record_bands(ra[k], ta, y0, rows, H) : 0u) |
+                              (inb ? record_bands(rb[k], tb, y0, rows, H) : 0u);
+          m |= mk << (4 * k);
+        }
       }
+      const unsigned need = wave_or(m);
       if (need == 0u) continue;
       int pos = 0;
       if (lane == 0) pos = atomicAdd(slow + 4, __popc(need));
-      pos = __shfl(pos, 0) + __popc(need & ((1u << (lane & 7)) - 1u));
-      if (lane < 8 && ((need >> lane) & 1u) && pos < total) {
-        queue[2 * pos] = f.ltile0 + (tr0 + lane) * f.lcols + lt;
-        queue[2 * pos + 1] = fidx;
+      pos = __shfl(pos, 0) + __popc(need & ((1u << (lane & 31)) - 1u));
+      if (lane < 32 && ((need >> lane) & 1u) && pos < kBandsPerTile * total) {
+        queue[2 * pos] = f.ltile0 + (tr0 + lane / 4) * f.lcols + lt;
+        queue[2 * pos + 1] = fidx | ((lane & 3) << 24);
       }
     }
   }
 }
 
-// bits of the bands (kBandRows rows) that rows lo .. hi of a tile touch
-constexpr int kBandRows = 32;
-__device__ __forceinline__ unsigned band_bits(int lo, int hi) {
-  return (2u << (hi / kBandRows)) - (1u << (lo / kBandRows));
-}
-constexpr int kFillSparse = 48;   // cells of a tile filled one by one; beyond: per band, separably
-constexpr int kFillScan = 2048;   // hole rows of a tile checked one by one; beyond: per band, separably
+constexpr int kFillSparse = 48;   // cells of a band filled one by one; beyond: separably
+constexpr int kFillScan = 2048;   // hole rows of a band checked one by one; beyond: separably
 
 // window_max for up to NC cells of one phase-1 tile at once (pos: y * W + x,
 // nc of them valid), every load issued before the first is used; the tops
@@ -1107,12 +1129,12 @@ __device__ __forceinline__ void window_max_n(const FrameDesc& f, const KParams& 
   }
 }
 
-// One workgroup per queued tile.  Its column records and tops give the
-// leading empty rows and the columns with holes; the hole rows are checked
+// One workgroup per queued band (kBandRows rows of a phase-1 tile).  The
+// column records and tops give each column's leading rows and whether holes
+// follow its first non-empty row; the hole rows within the band are checked
 // cell by cell (all threads over the flattened list of hole-column rows).
-// Up to kFillSparse cells then each take the window max (window_max, one
-// wave per cell); a tile with more fills its bands that hold such cells
-// separably (fill_region).
+// Up to kFillSparse cells then each take the window max (window_max_n, three
+// per wave at a time); a band with more is filled separably (fill_region).
 __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fill_tiles(FrameSource src, KParams kp, int lth) {
   constexpr int SR = kBandRows + 2 * kFillRad;
   __shared__ int S[SR * kDW];
@@ -1120,75 +1142,75 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
   __shared__ int s_list[kFillSparse];
   __shared__ short s_hcol[kLocalTW], s_hfirst[kLocalTW];
   __shared__ int s_n, s_lead, s_nh, s_cand;
-  __shared__ unsigned s_bands;
   const int tid = threadIdx.x, lane = tid & (kLanes - 1), wv = tid / kLanes;
   const int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int gcap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int lcap = src.plan ? src.plan->ltiles : src.single_ltiles;
-  const int count = min(slow[4], lcap);
+  const int count = min(slow[4], kBandsPerTile * lcap);
   const int32_t* queue = slow + fill_queue_offset(gcap);
   const int kthr = key(kp.thr);
   const int rl = kp.rl;
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
-    const int t = queue[2 * i], fidx = queue[2 * i + 1];
+    const int t = queue[2 * i], e1 = queue[2 * i + 1];
+    const int fidx = e1 & 0xffffff, band = (unsigned)e1 >> 24;
     FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
     f = uniform_frame(f);
     const int H = f.H, W = f.W;
     const int lt = t - f.ltile0, tr = lt / f.lcols, tc = lt - tr * f.lcols;
     const int y0 = tr * lth, x0 = tc * kLocalTW;
     const int rows = min(lth, H - y0), cols = min(kLocalTW, W - x0);
+    const int b0 = band * kBandRows, b1 = min(b0 + kBandRows, rows);   // the band's rows within the tile
     gcint* v4 = gc(f.v4);
     gint* v4w = gw(f.v4);
-    __syncthreads();                                   // LDS of the previous tile is no longer read
+    __syncthreads();                                   // LDS of the previous band is no longer read
     if (tid == 0) {
       s_n = 0;
       s_lead = 0;
       s_nh = 0;
       s_cand = 0;
-      s_bands = 0u;
     }
     // tops of the columns x0 - rl .. x0 - rl + kDW - 1 (clamped into the image)
     if (tid < kDW) s_top[tid] = kp.extrapolate ? gc(f.top)[clampi_s(x0 - rl + tid, 0, W - 1)] : H;
     const int x = x0 + tid;
     const int rec = tid < cols ? gc(f.v6p)[(size_t)tr * W + x] : 0;
     __syncthreads();
-    // this thread's column: its leading rows y0 .. y0 + lead - 1, and
-    // whether empty rows follow its first non-empty row
-    int lead = 0;
+    // this thread's column within the band: leading rows l0 .. l1 - 1 (tile
+    // rows), and whether empty rows may follow the first non-empty one
+    int l0 = 0, l1 = 0;
     if (tid < cols) {
       const int top = s_top[tid + rl];
       const int first = rec & 0xffff;
-      if ((top >= H || top < y0) && first != 0) lead = first == kRecNone ? rows : first;
-      unsigned bm = 0u;
-      if (lead > 0) {
-        bm |= band_bits(0, lead - 1);
-        atomicAdd(&s_lead, lead);
+      if ((top >= H || top < y0) && first != 0) {
+        l0 = b0;
+        l1 = min(b1, first == kRecNone ? rows : first);
+        if (l1 > l0) atomicAdd(&s_lead, l1 - l0);
       }
-      if (((unsigned)rec >> 16) == kRecHole && first + 1 < rows) {
-        bm |= band_bits(first + 1, rows - 1);
-        const int k = atomicAdd(&s_nh, 1);
-        s_hcol[k] = (short)tid;
-        s_hfirst[k] = (short)first;
-        atomicAdd(&s_cand, rows - 1 - first);
+      if ((((unsigned)rec >> 16) >> band) & 1u) {     // empty rows after the first non-empty one, in this band
+        const int h0 = max(first + 1, b0);
+        if (h0 < b1) {
+          const int k = atomicAdd(&s_nh, 1);
+          s_hcol[k] = (short)tid;
+          s_hfirst[k] = (short)h0;
+          atomicAdd(&s_cand, b1 - h0);
+        }
       }
-      if (bm) atomicOr(&s_bands, bm);
     }
     __syncthreads();
     bool dense = s_lead > kFillSparse || s_lead + s_cand > kFillScan;
     if (!dense) {
-      for (int k = 0; k < lead; ++k) {
+      for (int r = l0; r < l1; ++r) {
         const int j = atomicAdd(&s_n, 1);
-        if (j < kFillSparse) s_list[j] = (y0 + k) * W + x;
+        if (j < kFillSparse) s_list[j] = (y0 + r) * W + x;
       }
-      // hole rows: the rows of every hole column, flattened over the threads
-      const int nh = s_nh;
+      // hole rows: the band's rows of every hole column, flattened over the threads
+      const int nh = s_nh, nb = b1 - b0;
 #pragma unroll 4
-      for (int idx = tid; idx < nh * rows; idx += kDenseThreads) {
-        const int k = idx / rows, r = idx - k * rows;
+      for (int idx = tid; idx < nh * nb; idx += kDenseThreads) {
+        const int k = idx / nb, r = b0 + idx - k * nb;
         const int c = s_hcol[k];
         const int y = y0 + r, xx = x0 + c;
         const int v = v4[(size_t)y * W + xx];
-        if (r > s_hfirst[k] && v <= kthr) {
+        if (r >= s_hfirst[k] && v <= kthr) {
           const int j = atomicAdd(&s_n, 1);
           if (j < kFillSparse) s_list[j] = y * W + xx;
         }
@@ -1213,15 +1235,10 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         }
       }
     } else {
-      const unsigned bands = s_bands;
-      for (int b = 0; b * kBandRows < rows; ++b) {
-        if (((bands >> b) & 1u) == 0u) continue;
-        const int by0 = y0 + b * kBandRows;
-        fill_region<kBandRows>(f, kp, by0, min(kBandRows, y0 + rows - by0), x0, cols, S, s_top, tid,
-                               [&](int y, int xx, int m) {
-                                 if (m > 0) v4w[(size_t)y * W + xx] = m | kFillTag;
-                               });
-      }
+      fill_region<kBandRows>(f, kp, y0 + b0, b1 - b0, x0, cols, S, s_top, tid,
+                             [&](int y, int xx, int m) {
+                               if (m > 0) v4w[(size_t)y * W + xx] = m | kFillTag;
+                             });
     }
   }
 }
