@@ -105,9 +105,12 @@ typedef struct {
 void ipb_params_default(ipb_params* p);
 
 /* Workspace bytes one frame of H x W needs: the stage-4 map, a map for the
- * large-fill values of cells left empty after the extension, one int32 per
- * column and the queues of the tile quarters and cells that need the large
- * fill.  Returns 0 for invalid sizes or parameters. */
+ * large-fill values of cells left empty after the extension (its start also
+ * holds the phase-1 column records), one int32 per column and the queues of
+ * the tiles, bands and cells that need the large fill.  With tile_local 0 a
+ * frame too small to give the GPU a wave per SIMD with 64-row phase-1 tiles
+ * takes 32-row ones, here and in the calls below.  Returns 0 for invalid
+ * sizes or parameters. */
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p);
 
 /* Complete one frame: depth_in (H x W, device) -> depth_out (H x W, device).
@@ -141,8 +144,11 @@ typedef struct {
 } ipb_frame;
 
 /* Workspace for a batch: the launch plan, then per frame what
- * ipb_workspace_bytes lists.  Returns 0 if any frame is invalid, two frames'
- * outputs overlap another frame's buffers, or n < 1. */
+ * ipb_workspace_bytes lists.  With tile_local 0 it covers both layouts a
+ * batch may take: ipb_complete_batch's (32-row phase-1 tiles when the frames
+ * are too few to give the GPU a wave per SIMD with 64-row tiles) and
+ * ipb_batch_plan's (the default tiles).  Returns 0 if any frame is invalid,
+ * two frames' outputs overlap another frame's buffers, or n < 1. */
 size_t ipb_batch_workspace_bytes(const ipb_frame* frames, int n, const ipb_params* p);
 
 /* Complete n frames (host array of descriptors with device pointers).  The

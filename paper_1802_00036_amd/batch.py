@@ -16,6 +16,7 @@ the plan only tells the kernels where each frame's tiles start.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 from typing import List, Optional, Sequence, Tuple
 
 import torch
@@ -24,6 +25,7 @@ from . import _lib as L
 from .api import Params, _check_map, _stream_handle, _workspace, frames_array
 
 Shape = Tuple[int, int]
+AUTO_TILE_WAVES = 1024   # 256 CUs x 4 SIMDs
 
 
 def _tile_counts(p: L.CParams, shapes: Sequence[Shape]) -> Tuple[int, int, int]:
@@ -69,9 +71,17 @@ class GraphBatch:
         if not capacity:
             raise ValueError("capacity must name at least one frame shape")
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.params = params or Params()
-        self.cp = self.params.to_c()
         self.capacity = [tuple(int(v) for v in s) for s in capacity]
+        params = params or Params()
+        if params.tile_local == 0:
+            # as the library does for calls that see their frames: 32-row
+            # phase-1 tiles when 64-row ones would give the GPU fewer waves
+            # than it has SIMDs (the plan and the captured launch share it)
+            lt64, _, _ = _tile_counts(params.to_c(), self.capacity)
+            if lt64 < AUTO_TILE_WAVES:
+                params = dataclasses.replace(params, tile_local=7)
+        self.params = params
+        self.cp = self.params.to_c()
         self.max_frames = len(self.capacity)
         self.max_lt, self.max_gt, self.max_cols = _tile_counts(self.cp, self.capacity)
         self.ws_bytes = shapes_workspace_bytes(self.capacity, self.params)

@@ -135,6 +135,35 @@ int resolve(const ipb_params* p, Resolved* r) {
 
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// The default phase-1 tile for calls that know their frames: 32-row tiles
+// when 64-row ones would give the GPU fewer waves than its SIMDs can hold
+// one each of (1024 on MI355X), so that small launches (one frame) spread
+// over more waves.  Calls that only see a plan keep the 64-row default, as
+// the plan was built with it.
+constexpr long long kAutoTileWaves = 1024;
+void auto_local_tile(const ipb_params* p, Resolved* r, long long tiles64) {
+  if (p->tile_local != 0 || !r->lstream || r->ltile != 5 || tiles64 >= kAutoTileWaves) return;
+  r->ltile = 7;
+  r->lth = stream_local_tile_rows(7);
+  r->ltw = stream_local_tile_cols(7);
+}
+
+int resolve_single(const ipb_params* p, int H, int W, Resolved* r) {
+  const int st = resolve(p, r);
+  if (st == IPB_OK && size_ok(H, W)) auto_local_tile(p, r, (long long)cdiv(W, r->ltw) * cdiv(H, r->lth));
+  return st;
+}
+
+int resolve_frames(const ipb_params* p, const ipb_frame* frames, int n, Resolved* r) {
+  const int st = resolve(p, r);
+  if (st != IPB_OK || frames == nullptr || n < 1) return st;
+  long long t = 0;
+  for (int i = 0; i < n; ++i)
+    if (size_ok(frames[i].H, frames[i].W)) t += (long long)cdiv(frames[i].W, r->ltw) * cdiv(frames[i].H, r->lth);
+  auto_local_tile(p, r, t);
+  return st;
+}
+
 // Per-device facts: CU count and resident workgroups per kernel variant.
 struct DeviceFacts {
   int cus = 0;
@@ -402,7 +431,7 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
 int run_single(const float* in, int H, int W, const ipb_params* p, float* out, int last_stage, void* ws,
                size_t ws_bytes, hipStream_t s) {
   Resolved r;
-  int st = resolve(p, &r);
+  int st = resolve_single(p, H, W, &r);
   if (st != IPB_OK) return st;
   if (in == nullptr || out == nullptr || !size_ok(H, W)) return IPB_ERR_INVALID_ARG;
   if (last_stage < 1 || last_stage > 9) return IPB_ERR_INVALID_ARG;
@@ -423,11 +452,8 @@ int run_single(const float* in, int H, int W, const ipb_params* p, float* out, i
   return launch_phases(src, r, -1, last_stage, src.single_ltiles, src.single_gtiles, W, false, H < 3 || W < 3, s);
 }
 
-int planned(const void* plan_dev, const ipb_params* p, int phase, int max_tiles_local, int max_tiles_global,
+int planned(const void* plan_dev, const Resolved& r, int phase, int max_tiles_local, int max_tiles_global,
             int max_cols, bool may_tiny, void* stream) {
-  Resolved r;
-  int st = resolve(p, &r);
-  if (st != IPB_OK) return st;
   if (plan_dev == nullptr || phase < -1 || phase > 5) return IPB_ERR_INVALID_ARG;
   if (max_tiles_local < 1 || max_tiles_global < 1 || max_cols < 1) return IPB_ERR_INVALID_ARG;
   FrameSource src;
@@ -466,7 +492,7 @@ void ipb_params_default(ipb_params* p) {
 
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p) {
   Resolved r;
-  if (resolve(p, &r) != IPB_OK || !size_ok(H, W)) return 0;
+  if (resolve_single(p, H, W, &r) != IPB_OK || !size_ok(H, W)) return 0;
   return frame_ws_bytes(H, W, r);
 }
 
@@ -482,7 +508,7 @@ int ipb_complete_stage(const float* depth_in, int H, int W, const ipb_params* p,
 
 int ipb_complete(const float* depth_in, int H, int W, const ipb_params* p, float* depth_out, void* stream) {
   Resolved r;
-  int st = resolve(p, &r);
+  int st = resolve_single(p, H, W, &r);
   if (st != IPB_OK) return st;
   if (depth_in == nullptr || depth_out == nullptr || !size_ok(H, W)) return IPB_ERR_INVALID_ARG;
   const size_t nb = sizeof(float) * (size_t)H * W;
@@ -505,9 +531,12 @@ size_t ipb_batch_plan_bytes(int n) {
 }
 
 size_t ipb_batch_workspace_bytes(const ipb_frame* frames, int n, const ipb_params* p) {
-  Resolved r;
+  Resolved r, ra;
   if (resolve(p, &r) != IPB_OK || check_frames(frames, n) != IPB_OK) return 0;
-  return batch_bytes(frames, n, r);
+  resolve_frames(p, frames, n, &ra);
+  // enough for ipb_complete_batch (which may take 32-row phase-1 tiles for
+  // few frames) and for a plan of ipb_batch_plan (the default tiles)
+  return std::max(batch_bytes(frames, n, r), batch_bytes(frames, n, ra));
 }
 
 int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p, void* ws, size_t ws_bytes,
@@ -543,13 +572,16 @@ int ipb_plan_totals(const void* plan_host, int* n, int* tiles_local, int* tiles_
 int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase, int max_tiles_local,
                          int max_tiles_global, int max_cols, void* stream) {
   // a plan may be rewritten for other frames after the launch is captured
-  return planned(plan_dev, p, phase, max_tiles_local, max_tiles_global, max_cols, true, stream);
+  Resolved r;
+  const int st = resolve(p, &r);
+  if (st != IPB_OK) return st;
+  return planned(plan_dev, r, phase, max_tiles_local, max_tiles_global, max_cols, true, stream);
 }
 
 int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p, void* ws, size_t ws_bytes,
                        void* stream) {
   Resolved r;
-  int st = resolve(p, &r);
+  int st = resolve_frames(p, frames, n, &r);
   if (st != IPB_OK) return st;
   st = check_frames(frames, n);
   if (st != IPB_OK) return st;
@@ -598,7 +630,7 @@ int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p, void
   slot.pending = true;
   bool tiny = false;
   for (int i = 0; i < n; ++i) tiny = tiny || frames[i].H < 3 || frames[i].W < 3;
-  return planned(ws, p, -1, lt, gt, cols, tiny, stream);
+  return planned(ws, r, -1, lt, gt, cols, tiny, stream);
 }
 
 const char* ipb_status_string(int status) {

@@ -142,7 +142,7 @@ def test_batch_plan_layout():
         assert ptrs[i, 2] + 4 * H * W <= ws + nb
         assert (hw[i, 0], hw[i, 1]) == (H, W)
     # small workspace, overlapping outputs
-    assert lib.ipb_batch_plan(arr, 4, ctypes.byref(p), ctypes.c_void_p(ws), nb - 256, plan, pb) == L.IPB_ERR_WORKSPACE
+    assert lib.ipb_batch_plan(arr, 4, ctypes.byref(p), ctypes.c_void_p(ws), nb // 2, plan, pb) == L.IPB_ERR_WORKSPACE
     arr2 = _frames([(10, 10), (10, 10)])
     arr2[1].out = arr2[0].out + 16
     assert lib.ipb_batch_workspace_bytes(arr2, 2, ctypes.byref(p)) == 0
