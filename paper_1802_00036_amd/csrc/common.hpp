@@ -3,11 +3,13 @@
 // Two phases per frame (the column extension of Sec. III "Extension to Top
 // of Frame" makes row 0 of a column depend on the lowest rows, so the chain
 // is split where that global dependency sits):
-//   phase 1 (local):  stages 1-4 on LDS tiles with a halo; writes the stage-4
+//   phase 1 (local):  stages 1-4 on tiles with a halo; writes the stage-4
 //                     map and, per column, the topmost non-empty row (atomic
 //                     integer min);
-//   phase 2 (global): stages 5-9 on LDS tiles with a halo; reads the stage-4
+//   phase 2 (global): stages 5-9 on tiles with a halo; reads the stage-4
 //                     map and the column table, writes the output.
+// Each phase has streaming kernels (stream.hip, one wave per tile) and LDS
+// tile kernels (kernels.hip, one workgroup per tile).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -5,10 +5,18 @@
 // so the fast path uses no LDS and no barriers.
 //
 //   k_local_stream  : stages 1-4 (inversion, kernel dilation, 5x5 closing,
-//                     7x7 small fill); 128 input columns -> 108 output columns.
+//                     7x7 small fill); 128 input columns -> 108 output
+//                     columns; also the column tops and per tile column a
+//                     record (first non-empty row, bands holding holes).
+//   k_fill_scan,
+//   k_fill_tiles    : stage 6 ahead of phase 2 for the default chain: the
+//                     records and the final tops give the cells that are
+//                     empty after the extension; their 31x31 fill goes into
+//                     the stage-4 map, tagged.
 //   k_global_stream : stages 5, 7, 8, 9 (extension on load, 5x5 median,
 //                     Gaussian, output inversion); 128 input columns -> 120
-//                     output columns.  A tile whose needed cells still hold an
+//                     output columns.  Default chain: reads the filled map.
+//                     Other chains: a tile whose needed cells still hold an
 //                     empty pixel after the extension needs the 31x31 fill
 //                     (stage 6): its quarters are queued, and the empty
 //                     cells of quarters with few of them are queued one by
