@@ -68,6 +68,14 @@ __device__ __forceinline__ float val(int k) { return __int_as_float(k); }
 __device__ __forceinline__ void st16(gchar* base, unsigned off, unsigned short v) {
   *(__attribute__((address_space(1))) unsigned short*)(base + off) = v;
 }
+// Atomic or at a 32-bit byte offset from a (uniform) row base.  A global
+// atomic, not a flat one: a flat access counts against both the vector
+// memory and the LDS counters, and one on a conditional path inside the
+// row loop makes the compiler drain every prefetched load at the join.
+__device__ __forceinline__ void or_at(gchar* base, unsigned off, unsigned v) {
+  __hip_atomic_fetch_or((__attribute__((address_space(1))) unsigned*)(base + off), v, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // lane i receives lane i-1's value (lane 0 receives 0; its neighbours are
 // outside the tile's input columns and never feed an output)
@@ -343,9 +351,8 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         const bool hole_b = o4row && outb && ob <= kthr && first_b < o4;
         if (__builtin_expect(__ballot(hole_a || hole_b) != 0, 0)) {
           const unsigned bit = 1u << (16 + (o4 - ty0) / 32);
-          unsigned* rw = reinterpret_cast<unsigned*>(f.v6p) + (size_t)(ty0 / TH) * W;
-          if (hole_a) atomicOr(rw + ca, bit);
-          if (hole_b) atomicOr(rw + cb, bit);
+          if (hole_a) or_at(rec, ua, bit);
+          if (hole_b) or_at(rec, ub, bit);
         }
       }
       const unsigned ro = (unsigned)o4 * W4;
