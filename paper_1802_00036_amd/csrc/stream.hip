@@ -65,18 +65,6 @@ __device__ __forceinline__ int ldk(gcint* row, unsigned off) { return *(gcint*)(
 __device__ __forceinline__ float ldf(gcfloat* row, unsigned off) { return *(gcfloat*)((gcchar*)row + off); }
 __device__ __forceinline__ void stk(gint* row, unsigned off, int v) { *(gint*)((gchar*)row + off) = v; }
 __device__ __forceinline__ float val(int k) { return __int_as_float(k); }
-__device__ __forceinline__ void st16(gchar* base, unsigned off, unsigned short v) {
-  *(__attribute__((address_space(1))) unsigned short*)(base + off) = v;
-}
-// Atomic or at a 32-bit byte offset from a (uniform) row base.  A global
-// atomic, not a flat one: a flat access counts against both the vector
-// memory and the LDS counters, and one on a conditional path inside the
-// row loop makes the compiler drain every prefetched load at the join.
-__device__ __forceinline__ void or_at(gchar* base, unsigned off, unsigned v) {
-  __hip_atomic_fetch_or((__attribute__((address_space(1))) unsigned*)(base + off), v, __ATOMIC_RELAXED,
-                        __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // lane i receives lane i-1's value (lane 0 receives 0; its neighbours are
 // outside the tile's input columns and never feed an output)
 __device__ __forceinline__ int from_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
@@ -180,9 +168,10 @@ constexpr int kLocalTW = 2 * kLanes - 2 * kLocalHalo;  // 108
 
 // Writes the stage-4 map into f.v4 for the later stages (the stage hooks
 // 1-4 take the LDS kernel).  The per-row work keeps to few scalar
-// instructions: row checks are one unsigned compare, the column-top record
-// is a running minimum, and the stores are unconditional, the lanes with
-// nothing to store writing to a scratch slot just past the map.
+// instructions and no branch: row checks are one unsigned compare, the
+// column-top record is a running minimum, the hole bands a running or, and
+// the stores are unconditional, the lanes with nothing to store writing to a
+// scratch slot just past the map.
 template <int SHAPE, int RD, int TH>
 __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0, int tx0, int lane) {
   const int H = f.H, W = f.W;
@@ -219,26 +208,27 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   }
   int first_a = kNoTop, first_b = kNoTop;
   gint* dst = gw(f.v4);
-  // column records for the fill ahead of phase 2 (pack_record): the hole
-  // half is set here to "none" and overwritten on the rare rows that hold a
-  // hole; the first-row half is written at the end of the tile
+  // column records for the fill ahead of phase 2, written once at the end
+  // of the tile: the first non-empty row and the bands holding a hole
   gchar* rec = (gchar*)(char*)f.v6p + 4 * (size_t)(ty0 / TH) * W;   // uniform row base; lanes add ua / ub
-  if (outa) st16(rec, ua + 2, 0);
-  if (outb) st16(rec, ub + 2, 0);
   gcfloat* in = gcf(f.in);
   const unsigned W4 = 4u * (unsigned)W;
   const unsigned sink = (unsigned)H * W4;                 // scratch slot past the stage-4 map
   const unsigned uH = (unsigned)H;
 
-  // input rows are fetched 8 rows ahead of their use
-  float da[8], db[8];
+  // input rows are fetched 4 rows ahead of their use (a wave's row step
+  // takes about a microsecond; fewer registers keep five waves per SIMD)
+  float da[4], db[4];
+  // bands of the lane's columns that hold a hole (record bits 16..), set
+  // without a branch in the row loop
+  unsigned holes_a = 0u, holes_b = 0u;
   auto fetch = [&](int r, float& xa_, float& xb_) {
     const unsigned rowoff = (unsigned)clampi_s(q0 + r, 0, H - 1) * W4;
     xa_ = ldf(in, rowoff + la);
     xb_ = ldf(in, rowoff + lb);
   };
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
+  for (int u = 0; u < 4; ++u) {
     fetch(u, da[u], db[u]);
     __builtin_amdgcn_sched_barrier(0);   // keep the prefetch in row order
   }
@@ -256,13 +246,13 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       int va, vb;
       {
         const bool rin = (unsigned)q < uH;
-        const float x0 = detachf(da[u]), x1 = detachf(db[u]);
+        const float x0 = detachf(da[u & 3]), x1 = detachf(db[u & 3]);
         const float d0 = (rin && ina) ? x0 : 0.f, d1 = (rin && inb) ? x1 : 0.f;
-        fetch(r + 8, da[u], db[u]);
-        __builtin_amdgcn_sched_barrier(0);   // issue the prefetch here, eight rows ahead
+        fetch(r + 4, da[u & 3], db[u & 3]);
+        __builtin_amdgcn_sched_barrier(0);   // issue the prefetch here, four rows ahead
         const float v0 = off - d0, v1 = off - d1;
-        va = (d0 > thr && v0 > thr) ? key(v0) : 0;
-        vb = (d1 > thr && v1 > thr) ? key(v1) : 0;
+        va = fminf(d0, v0) > thr ? key(v0) : 0;
+        vb = fminf(d1, v1) > thr ? key(v1) : 0;
       }
 
       // Stage 2: kernel dilation; horizontal maxima of row q, then the
@@ -344,16 +334,14 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         ob = c3b <= kthr ? mb : c3b;
         // rows arrive in order, so the first non-empty row is a running minimum
         const int cand = o4row ? o4 : kNoTop;
-        first_a = min(first_a, (outa && oa > kthr) ? cand : kNoTop);
-        first_b = min(first_b, (outb && ob > kthr) ? cand : kNoTop);
-        // an empty cell below the column's first non-empty row of the tile
-        const bool hole_a = o4row && outa && oa <= kthr && first_a < o4;
-        const bool hole_b = o4row && outb && ob <= kthr && first_b < o4;
-        if (__builtin_expect(__ballot(hole_a || hole_b) != 0, 0)) {
-          const unsigned bit = 1u << (16 + (o4 - ty0) / 32);
-          if (hole_a) or_at(rec, ua, bit);
-          if (hole_b) or_at(rec, ub, bit);
-        }
+        const int cand_a = outa ? cand : kNoTop, cand_b = outb ? cand : kNoTop;
+        first_a = min(first_a, oa > kthr ? cand_a : kNoTop);
+        first_b = min(first_b, ob > kthr ? cand_b : kNoTop);
+        // an empty cell below the column's first non-empty row of the tile:
+        // oa <= kthr and first_a < o4, as one signed compare
+        const unsigned bit = (0x10000u << (((unsigned)(o4 - ty0) >> 5) & 15u)) & (o4row ? ~0u : 0u);
+        holes_a |= max(oa - kthr - 1, (int)((unsigned)first_a - (unsigned)o4)) < 0 ? bit : 0u;
+        holes_b |= max(ob - kthr - 1, (int)((unsigned)first_b - (unsigned)o4)) < 0 ? bit : 0u;
       }
       const unsigned ro = (unsigned)o4 * W4;
       stk(dst, (o4row && outa) ? ro + ua : sink, oa);
@@ -362,8 +350,8 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   }
   if (outa && first_a != kNoTop) atomicMin(f.top + ca, first_a);
   if (outb && first_b != kNoTop) atomicMin(f.top + cb, first_b);
-  if (outa) st16(rec, ua, record_first(first_a, ty0));
-  if (outb) st16(rec, ub, record_first(first_b, ty0));
+  if (outa) stk((gint*)rec, ua, (int)(holes_a | record_first(first_a, ty0)));
+  if (outb) stk((gint*)rec, ub, (int)(holes_b | record_first(first_b, ty0)));
 }
 
 template <int SHAPE, int RD, int TH>
