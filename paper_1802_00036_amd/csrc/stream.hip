@@ -493,10 +493,10 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
   int qempty[4] = {0, 0, 0, 0};
 
   // Stage 5 on load: rows of the stage-4 map (border rows replicated), the
-  // extension applied; fetched 8 rows ahead of their use.
+  // extension applied; fetched 4 rows ahead of their use.
   // PATCHED: the stage-6 value of the same cell, used where the stage-5
   // value is empty (such a cell is at or below its column's top).
-  int pa[8], pb[8], ppa[8], ppb[8];
+  int pa[4], pb[4], ppa[4], ppb[4];
   gcint* v6p = gc(f.v6p);
   auto fetch = [&](int r, int u_) {
     const unsigned rowoff = (unsigned)clampi_s(q0 + r, 0, H - 1) * W4;
@@ -516,7 +516,7 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
     }
   };
 #pragma unroll
-  for (int u = 0; u < 8; ++u) fetch(u, u);
+  for (int u = 0; u < 4; ++u) fetch(u, u);
 
   // One row step: row q = q0 + r enters, the median of row q - 2 and the
   // outputs of row q - 4 leave.  FAST: the default chain (5x5 median, 5x5
@@ -530,17 +530,17 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
     // FAST: cells the fill ahead of this pass completed carry kFillTag
     int va, vb;
     if constexpr (FAST) {
-      va = pa[u] & ~kFillTag;
-      vb = pb[u] & ~kFillTag;
+      va = pa[u & 3] & ~kFillTag;
+      vb = pb[u & 3] & ~kFillTag;
     } else {
-      va = detach(pa[u]);
-      vb = detach(pb[u]);
+      va = detach(pa[u & 3]);
+      vb = detach(pb[u & 3]);
     }
     if (PATCHED) {
-      va = va <= kthr ? detach(ppa[u]) : va;
-      vb = vb <= kthr ? detach(ppb[u]) : vb;
+      va = va <= kthr ? detach(ppa[u & 3]) : va;
+      vb = vb <= kthr ? detach(ppb[u & 3]) : vb;
     }
-    fetch(r + 8, u);
+    fetch(r + 4, u & 3);
     if (FAST || (q >= 0 && q < H)) {
       if (!FAST && !PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
         // row q is an input row of quarter k when k*QR - 4 <= q - ty0 < (k+1)*QR + 4
