@@ -167,6 +167,11 @@ class Batches:
         self.dev = torch.device("cuda:0")
         self.n = len(host_maps)
         self.shapes = [m.shape for m in host_maps]
+        # frames under 3 rows or columns take a launch step of their own (5);
+        # a batch without one leaves it out (ipb_complete_planned phase -2)
+        self.steps = list(range(len(PHASES)))
+        if all(H >= 3 and W >= 3 for H, W in self.shapes):
+            self.steps.remove(PHASES.index("k_global_slow"))
         self.px = sum(H * W for H, W in self.shapes)
         self.sets = []
         for _ in range(n_sets):
@@ -197,22 +202,28 @@ class Batches:
         in the same timed steps (two events per step; the other launch steps
         run between them unbracketed).  Per-step durations of every launch
         step come from a separate, untimed pass with events between all steps
-        (those events add a few microseconds per step)."""
+        (those events add a few microseconds per step).  The steps are those
+        the batch needs: the one of frames under 3 rows or columns only when
+        the batch holds such a frame."""
         torch = self.torch
+        whole = -1 if PHASES.index("k_global_slow") in self.steps else -2
         for i in range(warmup):
-            self.run_phase(self.sets[i % len(self.sets)], -1)
+            self.run_phase(self.sets[i % len(self.sets)], whole)
         # untimed pass: every launch step bracketed
         diag = max(5, min(steps, 50))
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(PHASES) + 1)] for _ in range(diag)]
+        ns = len(self.steps)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)] for _ in range(diag)]
         torch.cuda.synchronize()
         for i in range(diag):
             st = self.sets[i % len(self.sets)]
-            for ph in range(len(PHASES)):
-                evs[i][ph].record(self.stream)
+            for j, ph in enumerate(self.steps):
+                evs[i][j].record(self.stream)
                 self.run_phase(st, ph)
-            evs[i][len(PHASES)].record(self.stream)
+            evs[i][ns].record(self.stream)
         torch.cuda.synchronize()
-        k_ms = {name: sum(e[k].elapsed_time(e[k + 1]) for e in evs) / diag for k, name in enumerate(PHASES)}
+        k_ms = {name: 0.0 for name in PHASES}
+        for j, ph in enumerate(self.steps):
+            k_ms[PHASES[ph]] = sum(e[j].elapsed_time(e[j + 1]) for e in evs) / diag
         dom = max(BYTES_PER_PX, key=lambda k: k_ms[k])
         dph = PHASES.index(dom)
         # timed pass
@@ -223,7 +234,7 @@ class Batches:
         t0.record(self.stream)
         for i in range(steps):
             st = self.sets[i % len(self.sets)]
-            for ph in range(len(PHASES)):
+            for ph in self.steps:
                 if ph == dph:
                     ev[i][0].record(self.stream)
                     self.run_phase(st, ph)

@@ -176,7 +176,10 @@ int ipb_batch_plan(const ipb_frame* frames, int n, const ipb_params* p,
  * ipb_batch_plan with the same parameters p; max_tiles_local/global and
  * max_cols bound the plans it may be replayed with (the launch grids are
  * derived from them, so the call can be captured once and replayed).
- * phase: -1 = everything; else one launch step, in this order:
+ * phase: -1 = everything; -2 = everything but step 5, for callers that
+ * know no frame of the plans the call runs with has under 3 rows or columns
+ * (a tiny frame in such a plan is left incomplete); else one launch step, in
+ * this order:
  *   0 reset the column tables and the tile queues;
  *   1 stages 1-4;
  *   2 the default chain (Sec. III; Tables 2 and 3: 5x5 median, 5x5

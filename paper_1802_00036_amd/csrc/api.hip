@@ -575,6 +575,9 @@ int ipb_complete_planned(const void* plan_dev, const ipb_params* p, int phase, i
   Resolved r;
   const int st = resolve(p, &r);
   if (st != IPB_OK) return st;
+  // -2: every step but the one of frames under 3 rows or columns, which the
+  // caller guarantees none of its plans holds
+  if (phase == -2) return planned(plan_dev, r, -1, max_tiles_local, max_tiles_global, max_cols, false, stream);
   return planned(plan_dev, r, phase, max_tiles_local, max_tiles_global, max_cols, true, stream);
 }
 

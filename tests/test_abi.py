@@ -154,6 +154,8 @@ def test_batch_plan_layout():
     assert lib.ipb_batch_workspace_bytes(arr4, 1, ctypes.byref(p)) > 0
     assert lib.ipb_complete_planned(None, ctypes.byref(p), -1, 1, 1, 1, None) == L.IPB_ERR_INVALID_ARG
     assert lib.ipb_complete_planned(plan, ctypes.byref(p), 6, 1, 1, 1, None) == L.IPB_ERR_INVALID_ARG
+    assert lib.ipb_complete_planned(plan, ctypes.byref(p), -3, 1, 1, 1, None) == L.IPB_ERR_INVALID_ARG
+    assert lib.ipb_complete_planned(None, ctypes.byref(p), -2, 1, 1, 1, None) == L.IPB_ERR_INVALID_ARG
 
 
 def test_tile_table():

@@ -137,9 +137,10 @@ def test_quality_sweep_runs_every_design_step():
         [fr.dense_gt for fr in frames])["rmse_mm"], rtol=1e-3)
 
 
-def _planned_steps(frames, outs, p):
+def _planned_steps(frames, outs, p, steps=range(5)):
     """The bench's launch configuration: one plan for the whole batch, then
-    ipb_complete_planned one launch step at a time (steps 0-5)."""
+    ipb_complete_planned one launch step at a time (steps 0-4: no frame has
+    under 3 rows or columns); steps may also be [-1] or [-2]."""
     import ctypes
     from paper_1802_00036_amd import _lib as L
     lib = L.lib()
@@ -155,11 +156,31 @@ def _planned_steps(frames, outs, p):
     lib.ipb_plan_totals(ph, ctypes.byref(n), ctypes.byref(lt), ctypes.byref(gt), ctypes.byref(cols))
     pd = torch.frombuffer(bytearray(ph.raw), dtype=torch.uint8).to(frames[0].device)
     sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    for step in range(6):
+    for step in steps:
         L.check(lib.ipb_complete_planned(ctypes.c_void_p(pd.data_ptr()), ctypes.byref(cp), step, lt.value, gt.value,
                                          cols.value, sh), "ipb_complete_planned")
     torch.cuda.synchronize()
     del ws, pd
+
+
+@pytest.mark.parametrize("whole", [-1, -2])
+def test_planned_whole_launch(whole):
+    """ipb_complete_planned with every step at once (-1), and without the
+    step of frames under 3 rows or columns (-2) on frames that have none
+    (sizes down to 3 rows and 3 columns): each frame bitwise equal to the
+    frame completed alone."""
+    shapes = [(3, 200), (200, 3), (3, 3), (64, 64), (97, 300), (375, 1242)]
+    rng = np.random.default_rng(11)
+    frames = []
+    for H, W in shapes:
+        d = np.where(rng.random((H, W)) < 0.06, rng.uniform(1.0, 80.0, (H, W)), 0.0).astype(np.float32)
+        frames.append(torch.from_numpy(d).to(DEV))
+    outs = [torch.empty_like(t) for t in frames]
+    p = api.Params()
+    print(f"[planned whole {whole}] shapes {shapes}", flush=True)
+    _planned_steps(frames, outs, p, steps=[whole])
+    for i, (t, o) in enumerate(zip(frames, outs)):
+        assert np.array_equal(bits(o), bits(api.complete(t, p))), f"frame {i} {shapes[i]}: batch != alone"
 
 
 @pytest.mark.parametrize("cfg", [2, 4])
