@@ -13,9 +13,12 @@ Workloads (seeded synthetic LIDAR-shaped sparse depth maps, float32):
                 against the plain per-frame path
 
 One step = one batch through all nine stages.  Inputs are resident in HBM;
-three buffer sets (input, output, workspace) are rotated so the 256 MB
-Infinity Cache cannot serve a step from the previous one.  Prints one JSON
-line.
+at least three buffer sets (input, output, workspace) are rotated so the
+256 MB Infinity Cache cannot serve a step from the previous one.  The timed
+batches of the batched workloads are spread over --streams streams (3 by
+default), each buffer set bound to one of them, so independent batches
+overlap; the same batches on one stream are timed and reported too.  Prints
+one JSON line.
 """
 from __future__ import annotations
 
@@ -154,9 +157,12 @@ def valu_ceiling(kernel: str, workload: str, ms: float):
 
 
 class Batches:
-    """Rotating buffer sets of one batch (inputs, outputs, workspace, device plan)."""
+    """Rotating buffer sets of one batch (inputs, outputs, workspace, device
+    plan), each bound to one of n_streams streams (all at the default
+    priority).  Batches are independent, so batches on different streams may
+    run at once; a set is only ever used on its own stream."""
 
-    def __init__(self, host_maps, params, n_sets=3):
+    def __init__(self, host_maps, params, n_streams=1):
         import torch
         from paper_1802_00036_amd import _lib as L
         from paper_1802_00036_amd import api
@@ -173,8 +179,10 @@ class Batches:
         if all(H >= 3 and W >= 3 for H, W in self.shapes):
             self.steps.remove(PHASES.index("k_global_slow"))
         self.px = sum(H * W for H, W in self.shapes)
+        self.streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+        n_sets = n_streams * -(-3 // n_streams)        # at least three, a multiple of the streams
         self.sets = []
-        for _ in range(n_sets):
+        for k in range(n_sets):
             ins = [torch.from_numpy(m).to(self.dev) for m in host_maps]
             outs = [torch.empty_like(t) for t in ins]
             arr = api.frames_array(ins, outs)
@@ -187,38 +195,53 @@ class Batches:
             n, lt, gt, cols = (ctypes.c_int() for _ in range(4))
             self.lib.ipb_plan_totals(plan_h, ctypes.byref(n), ctypes.byref(lt), ctypes.byref(gt), ctypes.byref(cols))
             plan_d = torch.frombuffer(bytearray(plan_h.raw), dtype=torch.uint8).to(self.dev)
-            self.sets.append(dict(ins=ins, outs=outs, ws=ws, plan=plan_d, lt=lt.value, gt=gt.value, cols=cols.value))
-        self.stream = torch.cuda.current_stream()
+            s = self.streams[k % n_streams]
+            self.sets.append(dict(ins=ins, outs=outs, ws=ws, plan=plan_d, lt=lt.value, gt=gt.value, cols=cols.value,
+                                  stream=s))
+        self.stream = self.streams[0]
         self.sh = ctypes.c_void_p(self.stream.cuda_stream)
 
-    def run_phase(self, st, phase):
+    def run_phase(self, st, phase, stream=None):
+        s = stream if stream is not None else st["stream"]
         self.L.check(self.lib.ipb_complete_planned(ctypes.c_void_p(st["plan"].data_ptr()), ctypes.byref(self.cp),
-                                                   phase, st["lt"], st["gt"], st["cols"], self.sh),
+                                                   phase, st["lt"], st["gt"], st["cols"],
+                                                   ctypes.c_void_p(s.cuda_stream)),
                      "ipb_complete_planned")
 
     def time_planned(self, steps, warmup):
-        """Mean ms per batch over `steps` timed steps, and the dominant
-        kernel's mean duration from HIP events around it on the launch stream
-        in the same timed steps (two events per step; the other launch steps
-        run between them unbracketed).  Per-step durations of every launch
-        step come from a separate, untimed pass with events between all steps
-        (those events add a few microseconds per step).  The steps are those
-        the batch needs: the one of frames under 3 rows or columns only when
-        the batch holds such a frame."""
+        """Two timed passes of `steps` batches each.
+
+        Serial: every batch on one stream, one after the other; the dominant
+        kernel's mean duration comes from HIP events around it on that stream
+        in the same steps (two events per step; the other launch steps run
+        between them unbracketed).
+        Streams: batch i on the stream of buffer set i mod sets, so batches
+        on different streams overlap (one batch's small latency-bound steps
+        and kernel tails run beside another's large kernels).  The time is
+        from an event on the first stream, which the others wait for, to an
+        event on it after it has waited for all of them.
+
+        Per-step durations of every launch step come from a separate, untimed
+        serial pass with events between all steps (those events add a few
+        microseconds per step).  The steps are those the batch needs: the one
+        of frames under 3 rows or columns only when the batch holds such a
+        frame.  Returns the serial (ms per batch, dominant (name, ms)), the
+        streams' ms per batch, the per-step durations and the wall time of
+        the streams' pass."""
         torch = self.torch
         whole = -1 if PHASES.index("k_global_slow") in self.steps else -2
         for i in range(warmup):
             self.run_phase(self.sets[i % len(self.sets)], whole)
-        # untimed pass: every launch step bracketed
+        torch.cuda.synchronize()
+        # untimed serial pass: every launch step bracketed
         diag = max(5, min(steps, 50))
         ns = len(self.steps)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)] for _ in range(diag)]
-        torch.cuda.synchronize()
         for i in range(diag):
             st = self.sets[i % len(self.sets)]
             for j, ph in enumerate(self.steps):
                 evs[i][j].record(self.stream)
-                self.run_phase(st, ph)
+                self.run_phase(st, ph, self.stream)
             evs[i][ns].record(self.stream)
         torch.cuda.synchronize()
         k_ms = {name: 0.0 for name in PHASES}
@@ -226,26 +249,45 @@ class Batches:
             k_ms[PHASES[ph]] = sum(e[j].elapsed_time(e[j + 1]) for e in evs) / diag
         dom = max(BYTES_PER_PX, key=lambda k: k_ms[k])
         dph = PHASES.index(dom)
-        # timed pass
+        # timed serial pass
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        w0 = time.perf_counter()
         t0.record(self.stream)
         for i in range(steps):
             st = self.sets[i % len(self.sets)]
             for ph in self.steps:
                 if ph == dph:
                     ev[i][0].record(self.stream)
-                    self.run_phase(st, ph)
+                    self.run_phase(st, ph, self.stream)
                     ev[i][1].record(self.stream)
                 else:
-                    self.run_phase(st, ph)
+                    self.run_phase(st, ph, self.stream)
         t1.record(self.stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
+        serial_ms = t0.elapsed_time(t1) / steps
         dom_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
-        return t0.elapsed_time(t1) / steps, k_ms, (dom, dom_ms), wall
+        ref = [o.clone() for o in self.sets[0]["outs"]]
+        # timed pass over the streams
+        s0, others = self.streams[0], self.streams[1:]
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t0.record(s0)
+        for s in others:
+            s.wait_event(t0)
+        for i in range(steps):
+            self.run_phase(self.sets[i % len(self.sets)], whole)
+        for s in others:
+            e = torch.cuda.Event()
+            e.record(s)
+            s0.wait_event(e)
+        t1.record(s0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        if not all(torch.equal(a, b) for a, b in zip(ref, self.sets[0]["outs"])):
+            raise RuntimeError("batches spread over streams gave other outputs than the serial pass")
+        return (serial_ms, (dom, dom_ms)), t0.elapsed_time(t1) / steps, k_ms, wall
 
     def time_graph(self, steps, warmup):
         """Mean ms per batch through GraphBatch (plan rewrite + one graph replay)."""
@@ -332,12 +374,17 @@ def bench_batch(args, workload, cpu, serve_host=None):
                              "candidates_us": [(r["phase"], r["tile"], None if r["us"] is None else round(r["us"], 1))
                                                for r in report]}
         del probe
-    b = Batches(maps, params)
-    ms_step, k_ms, dom_timed, wall = b.time_planned(args.steps, args.warmup)
+    b = Batches(maps, params, n_streams=args.streams)
+    (serial_ms, dom_timed), ms_step, k_ms, wall = b.time_planned(args.steps, args.warmup)
     fps = b.n / (ms_step / 1e3)
+    rf = roofline(dom_timed, b.px, workload)
+    rf["measured_in"] = "the serial timed pass: the kernel alone on the GPU"
     extra.update({
         "config": None,
-        "roofline": roofline(dom_timed, b.px, workload),
+        "streams": args.streams,
+        "serial_path": {"frames_per_s": round(b.n / (serial_ms / 1e3), 1), "ms_per_batch": round(serial_ms, 5),
+                        "note": "the same batches on one stream, one after the other"},
+        "roofline": rf,
         "valu_ceiling": valu_ceiling(dom_timed[0], workload, dom_timed[1]),
         "cpu_baseline": cpu,
         "hbm_gbps_algorithmic_pipeline": round(16 * b.px / (ms_step / 1e3) / 1e9, 1),
@@ -446,6 +493,9 @@ def main() -> None:
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-frame-steps", type=int, default=10)
+    ap.add_argument("--streams", type=int, default=3,
+                    help="batched workloads: streams the timed batches are spread over (buffer sets are bound "
+                         "to streams; batches on different streams overlap)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated frames per size for serving")
     ap.add_argument("--no-serving", action="store_true", help="c2: skip the serving summary")
