@@ -363,13 +363,13 @@ def bench_batch(args, workload, cpu, serve_host=None):
     params = api.Params(max_depth=140.0) if cfg == 4 else api.Params()
     maps = [f.sparse for f in synth.config_frames(cfg)]
     extra = {}
-    # the library's default tiles are the autotuner's choice for the uniform
-    # 375x1242 batch; the uneven and the large-frame batches are tuned here
-    if (cfg in (3, 4) or args.tune) and not args.no_tune:
+    # tile shapes tuned for this batch, run as the timed pass runs it (batches
+    # in flight on args.streams streams)
+    if not args.no_tune:
         from paper_1802_00036_amd import autotune
         probe = [torch.from_numpy(m).to("cuda:0") for m in maps]
         report = []
-        params = autotune.tune(probe, params, reps=3, use_cache=False, report=report)
+        params = autotune.tune(probe, params, reps=3, use_cache=False, report=report, streams=args.streams)
         extra["autotune"] = {"tile_local": params.tile_local, "tile_global": params.tile_global,
                              "candidates_us": [(r["phase"], r["tile"], None if r["us"] is None else round(r["us"], 1))
                                                for r in report]}
@@ -500,7 +500,6 @@ def main() -> None:
     ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated frames per size for serving")
     ap.add_argument("--no-serving", action="store_true", help="c2: skip the serving summary")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")
-    ap.add_argument("--tune", action="store_true", help="autotune the tile shapes of c2 too")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain kernel reading and writing 256 MiB (calibrates rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE)")

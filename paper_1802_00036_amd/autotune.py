@@ -7,6 +7,11 @@ launch against the 256 compute units) and on the parameters (halo widths).
 `tune` times every supported shape on the caller's own frames, one phase at a
 time (phase-1 shape first with the automatic phase-2 shape, then phase-2
 shapes with the winner), and returns the parameters with the fastest pair.
+A caller that keeps several batches in flight on separate streams asks for
+that (streams > 1): the three fastest shapes of each phase are then paired
+and each pair is timed as whole batches spread over the streams, because
+there a shape that issues fewer instructions (taller tiles, less halo) can
+win although it fills the GPU less when it runs alone.
 
 Results are cached in a JSON file keyed by device, parameters and a coarse
 signature of the batch (frame count, pixel total and median size, each
@@ -134,21 +139,79 @@ class _Timer:
             s.synchronize()
         return total / reps
 
+    def throughput_us(self, p: Params, streams: int, reps: int) -> Optional[float]:
+        """Microseconds per batch with `streams` batches in flight, one per
+        stream (each with its own outputs, workspace and plan; the inputs are
+        shared and only read), or None if the parameters are unsupported."""
+        cp = p.to_c()
+        lib = L.lib()
+        dev0 = self.frames[0].device
+        lanes = []
+        for k in range(streams):
+            outs = [torch.empty_like(f) for f in self.frames] if k else self.outs
+            arr = frames_array(self.frames, outs)
+            ws_bytes = int(lib.ipb_batch_workspace_bytes(arr, self.n, ctypes.byref(cp)))
+            if ws_bytes == 0:
+                return None
+            ws = _workspace(ws_bytes, dev0)
+            host = torch.empty(self.plan_bytes, dtype=torch.uint8, pin_memory=True)
+            st = lib.ipb_batch_plan(arr, self.n, ctypes.byref(cp), ctypes.c_void_p(ws.data_ptr()), ws_bytes,
+                                    ctypes.c_void_p(host.data_ptr()), self.plan_bytes)
+            if st == L.IPB_ERR_UNSUPPORTED:
+                return None
+            L.check(st, "ipb_batch_plan")
+            n, lt, gt, cols = (ctypes.c_int() for _ in range(4))
+            lib.ipb_plan_totals(ctypes.c_void_p(host.data_ptr()), ctypes.byref(n), ctypes.byref(lt),
+                                ctypes.byref(gt), ctypes.byref(cols))
+            s = self.stream if k == 0 else torch.cuda.Stream(device=dev0)
+            dev = torch.empty(self.plan_bytes, dtype=torch.uint8, device=dev0)
+            with torch.cuda.stream(s):
+                dev.copy_(host, non_blocking=True)
+            lanes.append((s, dev, host, outs, ws, lt.value, gt.value, cols.value))
+
+        def launch(lane):
+            s, dev, _, _, _, lt, gt, cols = lane
+            L.check(lib.ipb_complete_planned(ctypes.c_void_p(dev.data_ptr()), ctypes.byref(cp), -1, lt, gt, cols,
+                                             _stream_handle(s)), "ipb_complete_planned")
+
+        for lane in lanes:                         # warm-up
+            launch(lane)
+        torch.cuda.synchronize(dev0)
+        s0 = lanes[0][0]
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s0)
+        for lane in lanes[1:]:
+            lane[0].wait_event(a)
+        for _ in range(reps):
+            for lane in lanes:
+                launch(lane)
+        for lane in lanes[1:]:
+            e = torch.cuda.Event()
+            e.record(lane[0])
+            s0.wait_event(e)
+        b.record(s0)
+        b.synchronize()
+        torch.cuda.synchronize(dev0)
+        return a.elapsed_time(b) * 1e3 / (reps * streams)
+
 
 def candidate_ids(phase: int) -> List[int]:
     return list(range(1, int(L.lib().ipb_tile_count(phase)) + 1))
 
 
 def tune(frames: Sequence[torch.Tensor], params: Optional[Params] = None, reps: int = 5,
-         use_cache: bool = True, report: Optional[list] = None) -> Params:
+         use_cache: bool = True, report: Optional[list] = None, streams: int = 1) -> Params:
     """Parameters with the fastest tile shapes for batches like `frames`
-    (outputs and results are unchanged by the choice)."""
+    (outputs and results are unchanged by the choice), run one at a time
+    (streams = 1) or `streams` batches in flight on as many streams."""
     p0 = params or Params()
     frames = list(frames)
     if not frames:
         return p0
     shapes = [tuple(f.shape) for f in frames]
     key = "|".join((device_signature(frames[0].device), params_signature(p0), batch_signature(shapes)))
+    if streams > 1:
+        key += f"|streams{streams}"
     path = cache_path()
     if use_cache:
         hit = _load_cache(path).get(key)
@@ -159,23 +222,43 @@ def tune(frames: Sequence[torch.Tensor], params: Optional[Params] = None, reps: 
         outs = [torch.empty_like(f) for f in frames]
     stream.wait_stream(torch.cuda.current_stream())
     timer = _Timer(frames, outs, stream)
-    best_l, t_l = None, None
+    times_l = {}
     for tl in candidate_ids(1):
         t = timer.time_us(dataclasses.replace(p0, tile_local=tl, tile_global=0), phases=(1, 2), reps=reps)
         if report is not None:
             report.append({"phase": 1, "tile": tl, "us": t})
-        if t is not None and (t_l is None or t < t_l):
-            best_l, t_l = tl, t
-    best_g, t_g = None, None
+        if t is not None:
+            times_l[tl] = t
+    best_l = min(times_l, key=times_l.get) if times_l else None
+    times_g = {}
     for tg in candidate_ids(2):
         t = timer.time_us(dataclasses.replace(p0, tile_local=best_l or 0, tile_global=tg), phases=(3, 4, 5),
                           reps=reps)
         if report is not None:
             report.append({"phase": 2, "tile": tg, "us": t})
-        if t is not None and (t_g is None or t < t_g):
-            best_g, t_g = tg, t
+        if t is not None:
+            times_g[tg] = t
+    best_g = min(times_g, key=times_g.get) if times_g else None
+    entry = {"us_local": times_l.get(best_l), "us_global": times_g.get(best_g)}
+    if streams > 1 and times_l and times_g:
+        top_l = sorted(times_l, key=times_l.get)[:3]
+        top_g = sorted(times_g, key=times_g.get)[:3]
+        pair_us = {}
+        for tl in top_l:
+            for tg in top_g:
+                t = timer.throughput_us(dataclasses.replace(p0, tile_local=tl, tile_global=tg), streams, reps)
+                if report is not None:
+                    report.append({"phase": f"{streams} streams", "tile": f"{tl}/{tg}", "us": t})
+                if t is not None:
+                    pair_us[(tl, tg)] = t
+        if pair_us:
+            # pairs within 1 % of the best are a tie (timing noise); of those,
+            # the one fastest with a batch alone on the GPU
+            fastest = min(pair_us.values())
+            ties = [k for k, t in pair_us.items() if t <= 1.01 * fastest]
+            best_l, best_g = min(ties, key=lambda k: times_l[k[0]] + times_g[k[1]])
+            entry = {"us_per_batch": pair_us[(best_l, best_g)], "streams": streams}
     tuned = dataclasses.replace(p0, tile_local=best_l or 0, tile_global=best_g or 0)
     if use_cache:
-        _store_cache(path, key, {"tile_local": tuned.tile_local, "tile_global": tuned.tile_global,
-                                 "us_local": t_l, "us_global": t_g})
+        _store_cache(path, key, {"tile_local": tuned.tile_local, "tile_global": tuned.tile_global, **entry})
     return tuned

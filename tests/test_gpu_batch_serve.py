@@ -3,6 +3,7 @@ autotuner and the serving loop, all through the C ABI: every result must be
 bit-identical to the same frame completed alone, which in turn equals the
 oracle (checked on a sample)."""
 import dataclasses
+import json
 
 import numpy as np
 import pytest
@@ -84,6 +85,25 @@ def test_autotune_picks_a_valid_pair_and_results_do_not_change(tmp_path, monkeyp
     assert any(r["us"] is not None for r in report)
     again = autotune.tune(frames, reps=2)              # from the cache
     assert (again.tile_local, again.tile_global) == (p.tile_local, p.tile_global)
+    outs = api.complete_batch(frames, p)
+    for f, o in zip(frames, outs):
+        assert np.array_equal(bits(o), bits(api.complete(f)))
+
+
+def test_autotune_for_batches_in_flight(tmp_path, monkeypatch):
+    """tune(streams=2): the pairs are timed as batches in flight on two
+    streams; the pick is a valid pair, cached apart from the one-stream
+    pick, and results do not change."""
+    monkeypatch.setenv("IPB_TUNE_CACHE", str(tmp_path / "tune.json"))
+    frames = [lidar(int(h), int(w), [24, i]) for i, (h, w) in enumerate([(256, 800), (375, 1242), (300, 1100)])]
+    report = []
+    p = autotune.tune(frames, reps=2, report=report, streams=2)
+    assert 1 <= p.tile_local <= 7 and 1 <= p.tile_global <= 7
+    pairs = [r for r in report if r["phase"] == "2 streams"]
+    assert pairs and any(r["us"] is not None for r in pairs)
+    assert f"{p.tile_local}/{p.tile_global}" in [r["tile"] for r in pairs]
+    cache = json.load(open(tmp_path / "tune.json"))
+    assert len(cache) == 1 and next(iter(cache)).endswith("|streams2")
     outs = api.complete_batch(frames, p)
     for f, o in zip(frames, outs):
         assert np.array_equal(bits(o), bits(api.complete(f)))
