@@ -364,13 +364,16 @@ def bench_batch(args, workload, cpu, serve_host=None):
     maps = [f.sparse for f in synth.config_frames(cfg)]
     extra = {}
     # tile shapes tuned for this batch, run as the timed pass runs it (batches
-    # in flight on args.streams streams)
+    # in flight on args.streams streams): the user cache's or the shipped
+    # table's entry, else tuned here
     if not args.no_tune:
         from paper_1802_00036_amd import autotune
         probe = [torch.from_numpy(m).to("cuda:0") for m in maps]
         report = []
-        params = autotune.tune(probe, params, reps=3, use_cache=False, report=report, streams=args.streams)
+        params = autotune.tune(probe, params, reps=3, use_cache=not args.retune, report=report,
+                               streams=args.streams)
         extra["autotune"] = {"tile_local": params.tile_local, "tile_global": params.tile_global,
+                             "source": "tuned in this run" if report else "cached or shipped entry for this batch",
                              "candidates_us": [(r["phase"], r["tile"], None if r["us"] is None else round(r["us"], 1))
                                                for r in report]}
         del probe
@@ -500,6 +503,8 @@ def main() -> None:
     ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated frames per size for serving")
     ap.add_argument("--no-serving", action="store_true", help="c2: skip the serving summary")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune now instead of taking the cached or shipped entry for the batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain kernel reading and writing 256 MiB (calibrates rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE)")

@@ -16,9 +16,11 @@ win although it fills the GPU less when it runs alone.
 Results are cached in a JSON file keyed by device, parameters and a coarse
 signature of the batch (frame count, pixel total and median size, each
 rounded), so one tuning serves every batch of the same kind.  The cache path
-is $IPB_TUNE_CACHE, else ~/.cache/ipb/tune.json; tuning never changes
-results, only speed (every tile shape is bit-exact against the same
-definition).
+is $IPB_TUNE_CACHE, else ~/.cache/ipb/tune.json.  A table of such entries
+measured on MI355X for the benchmark batches ships beside this module
+(tuned_mi355x.json, written by `python -m paper_1802_00036_amd.autotune`);
+it is read when the user cache has no entry.  Tuning never changes results,
+only speed (every tile shape is bit-exact against the same definition).
 """
 from __future__ import annotations
 
@@ -33,6 +35,9 @@ import torch
 
 from . import _lib as L
 from .api import Params, _stream_handle, _workspace, frames_array
+
+
+SHIPPED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
 
 
 def cache_path() -> str:
@@ -214,7 +219,7 @@ def tune(frames: Sequence[torch.Tensor], params: Optional[Params] = None, reps: 
         key += f"|streams{streams}"
     path = cache_path()
     if use_cache:
-        hit = _load_cache(path).get(key)
+        hit = _load_cache(path).get(key) or _load_cache(SHIPPED_TABLE).get(key)
         if hit:
             return dataclasses.replace(p0, tile_local=int(hit["tile_local"]), tile_global=int(hit["tile_global"]))
     stream = torch.cuda.Stream(device=frames[0].device)
@@ -252,13 +257,45 @@ def tune(frames: Sequence[torch.Tensor], params: Optional[Params] = None, reps: 
                 if t is not None:
                     pair_us[(tl, tg)] = t
         if pair_us:
-            # pairs within 1 % of the best are a tie (timing noise); of those,
-            # the one fastest with a batch alone on the GPU
+            # pairs within 3 % of the best are a tie (the spread of repeated
+            # timings); of those, the one fastest with a batch alone on the GPU
             fastest = min(pair_us.values())
-            ties = [k for k, t in pair_us.items() if t <= 1.01 * fastest]
+            ties = [k for k, t in pair_us.items() if t <= 1.03 * fastest]
             best_l, best_g = min(ties, key=lambda k: times_l[k[0]] + times_g[k[1]])
             entry = {"us_per_batch": pair_us[(best_l, best_g)], "streams": streams}
     tuned = dataclasses.replace(p0, tile_local=best_l or 0, tile_global=best_g or 0)
     if use_cache:
         _store_cache(path, key, {"tile_local": tuned.tile_local, "tile_global": tuned.tile_global, **entry})
     return tuned
+
+
+def _write_table(path: str, streams: int, reps: int) -> None:
+    """Tune the benchmark batches (synth workloads 2, 3 and 4) for `streams`
+    batches in flight and write their entries to `path`."""
+    from . import synth
+    table = {}
+    for cfg in (2, 3, 4):
+        frames = [torch.from_numpy(f.sparse).to("cuda:0") for f in synth.config_frames(cfg)]
+        p0 = Params(max_depth=140.0) if cfg == 4 else Params()
+        os.environ["IPB_TUNE_CACHE"] = path + ".tmp"
+        report: list = []
+        tuned = tune(frames, p0, reps=reps, use_cache=True, report=report, streams=streams)
+        for r in report:
+            print(f"  {r['phase']}: tile {r['tile']}: {r['us']} us", flush=True)
+        entries = _load_cache(path + ".tmp")
+        table.update(entries)
+        print(f"workload {cfg}: tiles {tuned.tile_local}/{tuned.tile_global}", flush=True)
+        del frames
+    os.remove(path + ".tmp")
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="write the shipped tuning table")
+    ap.add_argument("--out", default=SHIPPED_TABLE)
+    ap.add_argument("--streams", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=10)
+    a = ap.parse_args()
+    _write_table(a.out, a.streams, a.reps)
