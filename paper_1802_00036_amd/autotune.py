@@ -67,8 +67,10 @@ def params_signature(p: Params) -> str:
 
 
 def device_signature(device: torch.device) -> str:
+    """Architecture and compute-unit count (the marketing name is left out:
+    the runtime reports a generic one when its name table is missing)."""
     props = torch.cuda.get_device_properties(device)
-    return f"{props.name}-{getattr(props, 'gcnArchName', '')}-{props.multi_processor_count}"
+    return f"{getattr(props, 'gcnArchName', '')}-{props.multi_processor_count}"
 
 
 def _load_cache(path: str) -> Dict[str, dict]:
