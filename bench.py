@@ -289,8 +289,11 @@ class Batches:
             raise RuntimeError("batches spread over streams gave other outputs than the serial pass")
         return (serial_ms, (dom, dom_ms)), t0.elapsed_time(t1) / steps, k_ms, wall
 
-    def time_graph(self, steps, warmup):
-        """Mean ms per batch through GraphBatch (plan rewrite + one graph replay)."""
+    def time_graph(self, steps, warmup, chain=True):
+        """Mean ms per batch through GraphBatch (plan rewrite + one graph
+        replay), one engine per buffer set, each on its own stream; chained
+        (every batch after the previous one) or not (the engines' batches
+        overlap)."""
         torch = self.torch
         from paper_1802_00036_amd.batch import GraphBatch
         engines = [GraphBatch(self.shapes, self.params, device=self.dev) for _ in self.sets]
@@ -304,7 +307,7 @@ class Batches:
             k = i % len(self.sets)
             # one engine per buffer set; engines run on their own streams, so
             # chain them to keep batches in sequence
-            if last is not None:
+            if chain and last is not None:
                 engines[k].stream.wait_event(last)
             last = engines[k].run(self.sets[k]["ins"], self.sets[k]["outs"])
         torch.cuda.synchronize()
@@ -312,16 +315,21 @@ class Batches:
         return 1e3 * wall / steps, sum(e.replays for e in engines)
 
     def time_per_frame(self, reps):
-        """Mean ms for the batch as one ipb_complete_ws call per frame."""
+        """Mean ms for the batch as one ipb_complete_ws call per frame, with
+        the library's tiles for single frames (the batch's tuned tiles are
+        chosen for whole batches)."""
         torch, api, L = self.torch, self.api, self.L
         st = self.sets[0]
-        fws = api._workspace(max(api.workspace_bytes(H, W, self.params) for H, W in self.shapes), self.dev)
+        import dataclasses
+        single = dataclasses.replace(self.params, tile_local=0, tile_global=0)
+        cp = single.to_c()
+        fws = api._workspace(max(api.workspace_bytes(H, W, single) for H, W in self.shapes), self.dev)
         fnb = fws.numel()
 
         def once():
             for i, (H, W) in enumerate(self.shapes):
                 L.check(self.lib.ipb_complete_ws(ctypes.c_void_p(st["ins"][i].data_ptr()), H, W,
-                                                 ctypes.byref(self.cp), ctypes.c_void_p(st["outs"][i].data_ptr()),
+                                                 ctypes.byref(cp), ctypes.c_void_p(st["outs"][i].data_ptr()),
                                                  ctypes.c_void_p(fws.data_ptr()), fnb, self.sh), "ipb_complete_ws")
         for _ in range(2):
             once()
@@ -397,7 +405,12 @@ def bench_batch(args, workload, cpu, serve_host=None):
     })
     g_ms, replays = b.time_graph(max(10, args.steps // 2), 4)
     extra["graph_path"] = {"frames_per_s": round(b.n / (g_ms / 1e3), 1), "ms_per_batch": round(g_ms, 4),
-                           "replays": replays, "note": "host clock around plan rewrite + graph replay"}
+                           "replays": replays, "note": "host clock around plan rewrite + graph replay, "
+                                                       "batches one after another"}
+    g_ms, replays = b.time_graph(max(10, args.steps // 2), 4, chain=False)
+    extra["graph_path_overlapped"] = {"frames_per_s": round(b.n / (g_ms / 1e3), 1), "ms_per_batch": round(g_ms, 4),
+                                      "replays": replays, "note": f"{len(b.sets)} GraphBatch engines on their own "
+                                                                  "streams, batches overlapping"}
     if args.per_frame_steps > 0:
         pf_ms = b.time_per_frame(args.per_frame_steps)
         extra["per_frame_path"] = {"frames_per_s": round(b.n / (pf_ms / 1e3), 1), "ms_per_batch": round(pf_ms, 4)}
