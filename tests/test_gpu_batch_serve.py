@@ -203,6 +203,45 @@ def test_planned_whole_launch(whole):
         assert np.array_equal(bits(o), bits(api.complete(t, p))), f"frame {i} {shapes[i]}: batch != alone"
 
 
+def test_batches_in_flight_on_streams():
+    """Three batches in flight on three streams (each with its own outputs,
+    workspace and plan; the inputs shared, only read), several rounds as the
+    bench's timed pass runs them: every output bitwise equal to the frame
+    completed alone."""
+    import ctypes
+    from paper_1802_00036_amd import _lib as L
+    lib = L.lib()
+    rng = np.random.default_rng(31)
+    shapes = [(375, 1242), (200, 640), (96, 333), (375, 1242)]
+    frames = [lidar(H, W, [31, i], density=float(rng.uniform(0.03, 0.08))) for i, (H, W) in enumerate(shapes)]
+    p = dataclasses.replace(api.Params(), tile_local=6, tile_global=6)
+    cp = p.to_c()
+    lanes = []
+    for k in range(3):
+        outs = [torch.empty_like(f) for f in frames]
+        arr = api.frames_array(frames, outs)
+        nb = int(lib.ipb_batch_workspace_bytes(arr, len(frames), ctypes.byref(cp)))
+        ws = api._workspace(nb, frames[0].device)
+        pb = int(lib.ipb_batch_plan_bytes(len(frames)))
+        ph = ctypes.create_string_buffer(pb)
+        L.check(lib.ipb_batch_plan(arr, len(frames), ctypes.byref(cp), ctypes.c_void_p(ws.data_ptr()), nb, ph, pb),
+                "ipb_batch_plan")
+        n, lt, gt, cols = (ctypes.c_int() for _ in range(4))
+        lib.ipb_plan_totals(ph, ctypes.byref(n), ctypes.byref(lt), ctypes.byref(gt), ctypes.byref(cols))
+        pd = torch.frombuffer(bytearray(ph.raw), dtype=torch.uint8).to(frames[0].device)
+        lanes.append((torch.cuda.Stream(), outs, ws, pd, lt.value, gt.value, cols.value))
+    torch.cuda.synchronize()
+    print("[in flight] 3 streams x 6 rounds", flush=True)
+    for _ in range(6):
+        for s, outs, ws, pd, lt, gt, cols in lanes:
+            L.check(lib.ipb_complete_planned(ctypes.c_void_p(pd.data_ptr()), ctypes.byref(cp), -2, lt, gt, cols,
+                                             ctypes.c_void_p(s.cuda_stream)), "ipb_complete_planned")
+    torch.cuda.synchronize()
+    for k, (_, outs, *_rest) in enumerate(lanes):
+        for i, (f, o) in enumerate(zip(frames, outs)):
+            assert np.array_equal(bits(o), bits(api.complete(f))), f"stream {k} frame {i} {shapes[i]}"
+
+
 @pytest.mark.parametrize("cfg", [2, 4])
 def test_bench_configuration_full_batch(cfg):
     """The whole batch the bench times (64 x 375x1242; 16 x 1024x4096 with the
