@@ -203,6 +203,22 @@ def test_planned_whole_launch(whole):
         assert np.array_equal(bits(o), bits(api.complete(t, p))), f"frame {i} {shapes[i]}: batch != alone"
 
 
+def test_shipped_tuning_entry_is_found(tmp_path, monkeypatch):
+    """On MI355X the shipped table answers tune() for the 64 x 375x1242
+    benchmark batch at three streams: no candidate is timed."""
+    monkeypatch.setenv("IPB_TUNE_CACHE", str(tmp_path / "empty.json"))
+    frames = [torch.from_numpy(f.sparse).to(DEV) for f in synth.config_frames(2)]
+    table = json.load(open(autotune.SHIPPED_TABLE))
+    key = "|".join((autotune.device_signature(frames[0].device), autotune.params_signature(api.Params()),
+                    autotune.batch_signature([tuple(f.shape) for f in frames]), "streams3"))
+    if key not in table:
+        pytest.skip(f"not the device the table was measured on ({autotune.device_signature(frames[0].device)})")
+    report = []
+    p = autotune.tune(frames, report=report, streams=3)
+    assert report == []
+    assert (p.tile_local, p.tile_global) == (table[key]["tile_local"], table[key]["tile_global"])
+
+
 def test_batches_in_flight_on_streams():
     """Three batches in flight on three streams (each with its own outputs,
     workspace and plan; the inputs shared, only read), several rounds as the
