@@ -343,6 +343,26 @@ class Batches:
         return a.elapsed_time(b) / reps
 
 
+def copy_probe_gbps(reps=20):
+    """HBM bandwidth a plain streaming kernel attains here: torch.mul over
+    256 MiB in and 256 MiB out, mean of `reps` event-timed launches."""
+    import torch
+    src_t = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst_t = torch.empty_like(src_t)
+    for _ in range(3):
+        torch.mul(src_t, 2.0, out=dst_t)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        torch.mul(src_t, 2.0, out=dst_t)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src_t, dst_t
+    return round(2 * (256 << 20) / (ms / 1e3) / 1e9, 1)
+
+
 def roofline(dom_timed, px, workload):
     dom, ms = dom_timed
     achieved = BYTES_PER_PX[dom] * px / (ms / 1e3) / 1e9
@@ -390,6 +410,8 @@ def bench_batch(args, workload, cpu, serve_host=None):
     fps = b.n / (ms_step / 1e3)
     rf = roofline(dom_timed, b.px, workload)
     rf["measured_in"] = "the serial timed pass: the kernel alone on the GPU"
+    rf["copy_probe_gbps"] = copy_probe_gbps()
+    rf["frac_of_copy_probe"] = round(rf["achieved"] / rf["copy_probe_gbps"], 4)
     extra.update({
         "config": None,
         "streams": args.streams,
