@@ -5,8 +5,7 @@
 Workloads (seeded synthetic LIDAR-shaped sparse depth maps, float32):
   c2 (default)  64 x 375x1242, 4-6 % valid, one batched launch per phase
   c1            one 352x1216 frame: per-call latency
-  c3            128 frames of uneven sizes (H 256-512, W 768-2048), autotuned
-                tile shapes, the whole chain replayed as one HIP graph
+  c3            128 frames of uneven sizes (H 256-512, W 768-2048)
   c4            16 x 1024x4096, 3 % valid, 1-120 m, offset 140
   c5            serving: Poisson arrivals at 500 / 2000 / 8000 frames/s of a
                 size mix (and 16000 as an overload point), continuous batching
@@ -50,11 +49,11 @@ PARAMS_TEXT = "diamond5 close5 fill7 extend fill31 median5 gauss5(binomial)"
 WORKLOADS = {
     "c1": "one LIDAR-shaped sparse depth map, 352x1216 float32, 64 scan rows, 5 % valid, 1-80 m; per-call latency",
     "c2": "batch of 64 LIDAR-shaped sparse depth maps, 375x1242 float32, 64 scan rows, 4-6 % valid, 1-80 m; "
-          "one batched launch per phase",
+          "one batched launch per phase, tuned tiles, three batches in flight on three streams",
     "c3": "uneven batch of 128 LIDAR-shaped maps, H U{256..512} x W U{768..2048}, 32/64/128 scan rows, "
-          "2-10 % valid; autotuned tiles, one HIP graph replay per batch",
+          "2-10 % valid; one batched launch per phase, tuned tiles, three batches in flight on three streams",
     "c4": "16 LIDAR-shaped maps of 1024x4096, 128 scan rows, 3 % valid, 1-120 m (offset 140), empty sky "
-          "and occlusions; one batched launch per phase, autotuned tiles",
+          "and occlusions; one batched launch per phase, tuned tiles, three batches in flight on three streams",
     "c5": "serving: Poisson arrivals at 500/2000/8000 frames/s, sizes 352x1216/375x1242/512x2048/1024x4096 "
           "(0.4/0.3/0.2/0.1), 2-10 % valid; device-resident inputs (no host transfer), continuous batching "
           "against one ipb_complete_ws per request on one stream",
