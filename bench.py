@@ -290,25 +290,35 @@ class Batches:
 
     def time_graph(self, steps, warmup, chain=True):
         """Mean ms per batch through GraphBatch (plan rewrite + one graph
-        replay), one engine per buffer set, each on its own stream; chained
-        (every batch after the previous one) or not (the engines' batches
-        overlap)."""
+        replay), one engine per buffer set, each on its own stream: chained
+        (every batch after the previous one), or as a GraphPipeline (batch i
+        on engine i mod engines, the engines' batches overlapping)."""
         torch = self.torch
-        from paper_1802_00036_amd.batch import GraphBatch
-        engines = [GraphBatch(self.shapes, self.params, device=self.dev) for _ in self.sets]
-        for i in range(max(warmup, 2 * len(self.sets))):
-            k = i % len(self.sets)
-            engines[k].run(self.sets[k]["ins"], self.sets[k]["outs"])
+        from paper_1802_00036_amd.batch import GraphBatch, GraphPipeline
+        n = len(self.sets)
+        if chain:
+            engines = [GraphBatch(self.shapes, self.params, device=self.dev) for _ in self.sets]
+
+            def submit(i, last):
+                k = i % n
+                # engines run on their own streams: chain them to keep batches in sequence
+                if last is not None:
+                    engines[k].stream.wait_event(last)
+                return engines[k].run(self.sets[k]["ins"], self.sets[k]["outs"])
+        else:
+            pipe = GraphPipeline(self.shapes, self.params, engines=n, device=self.dev)
+            engines = pipe.engines
+
+            def submit(i, last):
+                return pipe.run(self.sets[i % n]["ins"], self.sets[i % n]["outs"])   # set i mod n on engine i mod n
+        last = None
+        for i in range(max(warmup, 2 * n)):
+            last = submit(i, last)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         last = None
         for i in range(steps):
-            k = i % len(self.sets)
-            # one engine per buffer set; engines run on their own streams, so
-            # chain them to keep batches in sequence
-            if chain and last is not None:
-                engines[k].stream.wait_event(last)
-            last = engines[k].run(self.sets[k]["ins"], self.sets[k]["outs"])
+            last = submit(i, last)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         return 1e3 * wall / steps, sum(e.replays for e in engines)
@@ -430,7 +440,7 @@ def bench_batch(args, workload, cpu, serve_host=None):
                                                        "batches one after another"}
     g_ms, replays = b.time_graph(max(10, args.steps // 2), 4, chain=False)
     extra["graph_path_overlapped"] = {"frames_per_s": round(b.n / (g_ms / 1e3), 1), "ms_per_batch": round(g_ms, 4),
-                                      "replays": replays, "note": f"{len(b.sets)} GraphBatch engines on their own "
+                                      "replays": replays, "note": f"GraphPipeline of {len(b.sets)} engines on their own "
                                                                   "streams, batches overlapping"}
     if args.per_frame_steps > 0:
         pf_ms = b.time_per_frame(args.per_frame_steps)

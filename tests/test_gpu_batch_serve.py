@@ -203,6 +203,31 @@ def test_planned_whole_launch(whole):
         assert np.array_equal(bits(o), bits(api.complete(t, p))), f"frame {i} {shapes[i]}: batch != alone"
 
 
+def test_graph_pipeline_matches_alone():
+    """GraphPipeline: batches of uneven frames on three engines in turn
+    (each engine's first two batches eager, one per pinned plan, later ones
+    graph replays), several batches in flight at once: every output bitwise
+    equal to the frame completed alone."""
+    rng = np.random.default_rng(41)
+    cap = [(300, 900), (200, 640), (375, 1242)]
+    pipe = batch.GraphPipeline(cap, engines=3)
+    jobs = []
+    for b in range(9):
+        shapes = [(int(rng.integers(100, 301)), int(rng.integers(300, 901))), (200, 640), (375, 1242)]
+        frames = [lidar(H, W, [41, b, i]) for i, (H, W) in enumerate(shapes)]
+        outs = [torch.empty_like(f) for f in frames]
+        jobs.append((frames, outs))
+    torch.cuda.synchronize()
+    print("[graph pipeline] 9 batches on 3 engines", flush=True)
+    events = [pipe.run(frames, outs) for frames, outs in jobs]
+    for e in events:
+        e.synchronize()
+    assert sum(e.replays for e in pipe.engines) == 3       # the third batch of each engine is a replay
+    for b, (frames, outs) in enumerate(jobs):
+        for i, (f, o) in enumerate(zip(frames, outs)):
+            assert np.array_equal(bits(o), bits(api.complete(f))), f"batch {b} frame {i}"
+
+
 def test_shipped_tuning_entry_is_found(tmp_path, monkeypatch):
     """On MI355X the shipped table answers tune() for the 64 x 375x1242
     benchmark batch at three streams: no candidate is timed."""
