@@ -109,8 +109,10 @@ void ipb_params_default(ipb_params* p);
  * holds the phase-1 column records), one int32 per column and the queues of
  * the tiles, bands and cells that need the large fill.  With tile_local 0 a
  * frame too small to give the GPU a wave per SIMD with 64-row phase-1 tiles
- * takes 32-row ones, here and in the calls below.  Returns 0 for invalid
- * sizes or parameters. */
+ * takes 32-row ones, and with tile_global 0 and the default chain (stages
+ * 1-4 and 5-9 on the streaming kernels, 5x5 median) one too small to do so
+ * with 32-row phase-2 tiles takes 16-row ones, here and in the calls below.
+ * Returns 0 for invalid sizes or parameters. */
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p);
 
 /* Complete one frame: depth_in (H x W, device) -> depth_out (H x W, device).
@@ -144,10 +146,10 @@ typedef struct {
 } ipb_frame;
 
 /* Workspace for a batch: the launch plan, then per frame what
- * ipb_workspace_bytes lists.  With tile_local 0 it covers both layouts a
- * batch may take: ipb_complete_batch's (32-row phase-1 tiles when the frames
- * are too few to give the GPU a wave per SIMD with 64-row tiles) and
- * ipb_batch_plan's (the default tiles).  Returns 0 if any frame is invalid,
+ * ipb_workspace_bytes lists.  With tile id 0 it covers both layouts a batch
+ * may take: ipb_complete_batch's (the smaller tiles of ipb_workspace_bytes
+ * when the frames are too few to give the GPU a wave per SIMD with the
+ * default ones) and ipb_batch_plan's (the default tiles).  Returns 0 if any frame is invalid,
  * two frames' outputs overlap another frame's buffers, or n < 1. */
 size_t ipb_batch_workspace_bytes(const ipb_frame* frames, int n, const ipb_params* p);
 
@@ -211,7 +213,9 @@ const char* ipb_status_string(int status);
 int ipb_last_hip_error(void);
 
 /* Tile shapes (rows, cols) of a tile id for phase 1 (local) or 2 (global);
- * returns IPB_ERR_INVALID_ARG for an unknown id.  Id 0 = automatic. */
+ * returns IPB_ERR_INVALID_ARG for an unknown id.  Id 0 = automatic.  Phase-2
+ * id 8 (16-row streaming tiles) serves the default chain only; with any
+ * other chain it is IPB_ERR_UNSUPPORTED. */
 int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols);
 
 /* Number of tile ids per phase (ids 1..count). */

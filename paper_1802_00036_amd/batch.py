@@ -39,10 +39,11 @@ def _tile_counts(p: L.CParams, shapes: Sequence[Shape]) -> Tuple[int, int, int]:
     return out[0], out[1], sum(W for _, W in shapes)
 
 
-def shapes_workspace_bytes(shapes: Sequence[Shape], params: Optional[Params] = None) -> int:
-    """ipb_batch_workspace_bytes for frames of these shapes.  The call reads
-    only sizes; the descriptors carry distinct placeholder addresses (every
-    frame in place) that are never dereferenced."""
+def _placeholder_bytes(shapes: Sequence[Shape], params: Params) -> int:
+    """ipb_batch_workspace_bytes for frames of these shapes (0: invalid or
+    unsupported).  The call reads only sizes; the descriptors carry distinct
+    placeholder addresses (every frame in place) that are never
+    dereferenced."""
     arr = (L.CFrame * len(shapes))()
     addr = 1 << 40
     for i, (H, W) in enumerate(shapes):
@@ -50,8 +51,13 @@ def shapes_workspace_bytes(shapes: Sequence[Shape], params: Optional[Params] = N
         arr[i].out = addr
         arr[i].H, arr[i].W = H, W
         addr += (4 * H * W + 255) // 256 * 256
-    p = (params or Params()).to_c()
-    nb = int(L.lib().ipb_batch_workspace_bytes(arr, len(shapes), ctypes.byref(p)))
+    p = params.to_c()
+    return int(L.lib().ipb_batch_workspace_bytes(arr, len(shapes), ctypes.byref(p)))
+
+
+def shapes_workspace_bytes(shapes: Sequence[Shape], params: Optional[Params] = None) -> int:
+    """ipb_batch_workspace_bytes for frames of these shapes."""
+    nb = _placeholder_bytes(shapes, params or Params())
     if nb == 0:
         L.check(L.IPB_ERR_INVALID_ARG, "ipb_batch_workspace_bytes")
     return nb
@@ -73,13 +79,17 @@ class GraphBatch:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.capacity = [tuple(int(v) for v in s) for s in capacity]
         params = params or Params()
-        if params.tile_local == 0:
-            # as the library does for calls that see their frames: 32-row
-            # phase-1 tiles when 64-row ones would give the GPU fewer waves
-            # than it has SIMDs (the plan and the captured launch share it)
-            lt64, _, _ = _tile_counts(params.to_c(), self.capacity)
-            if lt64 < AUTO_TILE_WAVES:
-                params = dataclasses.replace(params, tile_local=7)
+        # as the library does for calls that see their frames: 32-row
+        # phase-1 tiles when 64-row ones would give the GPU fewer waves than
+        # it has SIMDs, and 16-row phase-2 tiles (the default chain only) when
+        # 32-row ones would (the plan and the captured launch share them)
+        lt64, gt32, _ = _tile_counts(params.to_c(), self.capacity)
+        if params.tile_local == 0 and lt64 < AUTO_TILE_WAVES:
+            params = dataclasses.replace(params, tile_local=7)
+        if params.tile_global == 0 and gt32 < AUTO_TILE_WAVES:
+            small = dataclasses.replace(params, tile_global=8)
+            if _placeholder_bytes(self.capacity, small) > 0:
+                params = small
         self.params = params
         self.cp = self.params.to_c()
         self.max_frames = len(self.capacity)

@@ -39,7 +39,8 @@ struct Resolved {
   bool lstream, gstream;   // streaming kernels (tile ids 5-7) or LDS tile kernels (ids 1-4)
 };
 
-constexpr int kTileIds = 7;
+constexpr int kTileIdsLocal = 7;
+constexpr int kTileIdsGlobal = 8;   // id 8: 16-row streaming tiles, default chain only
 
 bool odd_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v % 2) == 1; }
 
@@ -60,8 +61,8 @@ int resolve(const ipb_params* p, Resolved* r) {
     return IPB_ERR_UNSUPPORTED;
   if (p->median_size != 0 && !odd_in(p->median_size, 3, 5)) return IPB_ERR_UNSUPPORTED;
   if (p->gauss_size != 0 && !odd_in(p->gauss_size, 3, 5)) return IPB_ERR_UNSUPPORTED;
-  if (p->tile_local < 0 || p->tile_local > kTileIds) return IPB_ERR_INVALID_ARG;
-  if (p->tile_global < 0 || p->tile_global > kTileIds) return IPB_ERR_INVALID_ARG;
+  if (p->tile_local < 0 || p->tile_local > kTileIdsLocal) return IPB_ERR_INVALID_ARG;
+  if (p->tile_global < 0 || p->tile_global > kTileIdsGlobal) return IPB_ERR_INVALID_ARG;
   if (p->blur != IPB_BLUR_GAUSSIAN && p->blur != IPB_BLUR_BILATERAL) return IPB_ERR_INVALID_ARG;
   if (!std::isfinite(p->bilateral_sigma_space) || !(p->bilateral_sigma_space > 0.f) ||
       !std::isfinite(p->bilateral_sigma_color) || !(p->bilateral_sigma_color > 0.f))
@@ -116,6 +117,9 @@ int resolve(const ipb_params* p, Resolved* r) {
   r->lstream = r->ltile >= 5;
   r->gstream = r->gtile >= 5;
   if ((r->lstream && !ls_ok) || (r->gstream && !gs_ok)) return IPB_ERR_UNSUPPORTED;
+  // 16-row phase-2 tiles exist for the default chain only (its phase 2 has
+  // no second pass, whose quarters would be 4 rows)
+  if (r->gtile == 8 && !(r->lstream && fast_chain(k))) return IPB_ERR_UNSUPPORTED;
   if (r->lstream) {
     r->lth = stream_local_tile_rows(r->ltile);
     r->ltw = stream_local_tile_cols(r->ltile);
@@ -135,32 +139,44 @@ int resolve(const ipb_params* p, Resolved* r) {
 
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// The default phase-1 tile for calls that know their frames: 32-row tiles
+// The default tiles for calls that know their frames: 32-row phase-1 tiles
 // when 64-row ones would give the GPU fewer waves than its SIMDs can hold
-// one each of (1024 on MI355X), so that small launches (one frame) spread
-// over more waves.  Calls that only see a plan keep the 64-row default, as
-// the plan was built with it.
+// one each of (1024 on MI355X), and for the default chain 16-row phase-2
+// tiles when 32-row ones would, so that small launches (one frame) spread
+// over more waves.  Calls that only see a plan keep the defaults, as the
+// plan was built with them.
 constexpr long long kAutoTileWaves = 1024;
-void auto_local_tile(const ipb_params* p, Resolved* r, long long tiles64) {
-  if (p->tile_local != 0 || !r->lstream || r->ltile != 5 || tiles64 >= kAutoTileWaves) return;
-  r->ltile = 7;
-  r->lth = stream_local_tile_rows(7);
-  r->ltw = stream_local_tile_cols(7);
+void auto_tiles(const ipb_params* p, Resolved* r, long long tiles_local, long long tiles_global) {
+  if (p->tile_local == 0 && r->lstream && r->ltile == 5 && tiles_local < kAutoTileWaves) {
+    r->ltile = 7;
+    r->lth = stream_local_tile_rows(7);
+    r->ltw = stream_local_tile_cols(7);
+  }
+  if (p->tile_global == 0 && r->gstream && r->gtile == 6 && tiles_global < kAutoTileWaves && r->lstream &&
+      fast_chain(r->kp)) {
+    r->gtile = 8;
+    r->gth = stream_global_tile_rows(8);
+    r->gtw = stream_global_tile_cols(8);
+  }
 }
 
 int resolve_single(const ipb_params* p, int H, int W, Resolved* r) {
   const int st = resolve(p, r);
-  if (st == IPB_OK && size_ok(H, W)) auto_local_tile(p, r, (long long)cdiv(W, r->ltw) * cdiv(H, r->lth));
+  if (st == IPB_OK && size_ok(H, W))
+    auto_tiles(p, r, (long long)cdiv(W, r->ltw) * cdiv(H, r->lth), (long long)cdiv(W, r->gtw) * cdiv(H, r->gth));
   return st;
 }
 
 int resolve_frames(const ipb_params* p, const ipb_frame* frames, int n, Resolved* r) {
   const int st = resolve(p, r);
   if (st != IPB_OK || frames == nullptr || n < 1) return st;
-  long long t = 0;
+  long long tl = 0, tg = 0;
   for (int i = 0; i < n; ++i)
-    if (size_ok(frames[i].H, frames[i].W)) t += (long long)cdiv(frames[i].W, r->ltw) * cdiv(frames[i].H, r->lth);
-  auto_local_tile(p, r, t);
+    if (size_ok(frames[i].H, frames[i].W)) {
+      tl += (long long)cdiv(frames[i].W, r->ltw) * cdiv(frames[i].H, r->lth);
+      tg += (long long)cdiv(frames[i].W, r->gtw) * cdiv(frames[i].H, r->gth);
+    }
+  auto_tiles(p, r, tl, tg);
   return st;
 }
 
@@ -448,6 +464,11 @@ int run_single(const float* in, int H, int W, const ipb_params* p, float* out, i
     r.lth = local_tile_rows(1);
     r.ltw = local_tile_cols(1);
   }
+  if (last_stage < 9 && r.gtile == 8) {  // stage hooks run the general phase 2, on 32-row tiles
+    r.gtile = 6;                          // (fewer tiles than the workspace was sized for)
+    r.gth = stream_global_tile_rows(6);
+    r.gtw = stream_global_tile_cols(6);
+  }
   FrameSource src = single_source(in, H, W, out, ws, r);
   return launch_phases(src, r, -1, last_stage, src.single_ltiles, src.single_gtiles, W, false, H < 3 || W < 3, s);
 }
@@ -652,7 +673,7 @@ int ipb_last_hip_error(void) { return g_last_hip; }
 int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols) {
   if (rows == nullptr || cols == nullptr) return IPB_ERR_INVALID_ARG;
   if (tile_id == 0) tile_id = phase == 1 ? 5 : 6;   // defaults of the streaming kernels
-  if (tile_id < 1 || tile_id > kTileIds) return IPB_ERR_INVALID_ARG;
+  if (tile_id < 1 || tile_id > (phase == 2 ? kTileIdsGlobal : kTileIdsLocal)) return IPB_ERR_INVALID_ARG;
   if (phase == 1) {
     *rows = tile_id >= 5 ? stream_local_tile_rows(tile_id) : local_tile_rows(tile_id);
     *cols = tile_id >= 5 ? stream_local_tile_cols(tile_id) : local_tile_cols(tile_id);
@@ -666,6 +687,6 @@ int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols) {
   return IPB_ERR_INVALID_ARG;
 }
 
-int ipb_tile_count(int phase) { return (phase == 1 || phase == 2) ? kTileIds : 0; }
+int ipb_tile_count(int phase) { return phase == 1 ? kTileIdsLocal : phase == 2 ? kTileIdsGlobal : 0; }
 
 }  // extern "C"

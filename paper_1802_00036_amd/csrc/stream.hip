@@ -1270,7 +1270,9 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 constexpr int stream_local_rows(int id) { return id == 5 ? 64 : id == 6 ? 128 : id == 7 ? 32 : 0; }
-constexpr int stream_global_rows(int id) { return id == 5 ? 64 : id == 6 ? 32 : id == 7 ? 128 : 0; }
+constexpr int stream_global_rows(int id) {
+  return id == 5 ? 64 : id == 6 ? 32 : id == 7 ? 128 : id == 8 ? 16 : 0;
+}
 
 template <class K>
 int occupancy_s(K kernel) {
@@ -1318,6 +1320,7 @@ hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int t
   if (tile_id == 5) { IPB_GS(64) }
   else if (tile_id == 6) { IPB_GS(32) }
   else if (tile_id == 7) { IPB_GS(128) }
+  else if (tile_id == 8) { IPB_GS(16) }
   else return hipErrorInvalidValue;
 #undef IPB_GS
   return hipGetLastError();
@@ -1326,7 +1329,9 @@ hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int t
 hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, int cell_grid,
                                 hipStream_t s) {
   // the fill values of the queued cells and of the dense quarters, then the
-  // second pass over both quarter queues
+  // second pass over both quarter queues (16-row tiles: the default chain
+  // only, which has no second pass)
+  if (tile_id == 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_fill_cells, dim3(cell_grid), dim3(kLanes), 0, s, src, kp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1378,6 +1383,7 @@ int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast)
   if (tile_id == 5) return fast ? occupancy_s(k_global_stream<64, true>) : occupancy_s(k_global_stream<64, false>);
   if (tile_id == 6) return fast ? occupancy_s(k_global_stream<32, true>) : occupancy_s(k_global_stream<32, false>);
   if (tile_id == 7) return fast ? occupancy_s(k_global_stream<128, true>) : occupancy_s(k_global_stream<128, false>);
+  if (tile_id == 8) return fast ? occupancy_s(k_global_stream<16, true>) : occupancy_s(k_global_stream<16, false>);
   return 1;
 }
 

@@ -158,6 +158,22 @@ def test_batch_plan_layout():
     assert lib.ipb_complete_planned(None, ctypes.byref(p), -2, 1, 1, 1, None) == L.IPB_ERR_INVALID_ARG
 
 
+def test_sixteen_row_phase2_tiles_and_their_automatic_use():
+    """Phase-2 tile id 8 (16 rows) serves the default chain only, and calls
+    that see their frames take it (with 32-row phase-1 tiles) when 32-row
+    phase-2 tiles would give the GPU fewer than 1024 waves."""
+    lib = L.lib()
+    ws = lambda H, W, **kw: int(lib.ipb_workspace_bytes(H, W, ctypes.byref(P(**kw))))
+    assert ws(352, 1216, tile_global=8) > 0
+    assert ws(352, 1216, tile_global=8, median_size=3) == 0            # not the default chain
+    assert ws(352, 1216, tile_global=8, tile_local=1) == 0             # LDS phase 1: not the default chain
+    # one 352x1216 frame: 11 x 11 phase-2 tiles of 32 rows, so the automatic choice is 16 rows
+    assert ws(352, 1216) == ws(352, 1216, tile_local=7, tile_global=8)
+    # one 1024x4096 frame: 32 x 35 = 1120 phase-2 tiles of 32 rows, so 32 rows stay
+    assert ws(1024, 4096) == ws(1024, 4096, tile_local=7, tile_global=6)
+    assert ws(1024, 4096) != ws(1024, 4096, tile_local=7, tile_global=8)
+
+
 def test_tile_table():
     lib = L.lib()
     for phase in (1, 2):

@@ -137,6 +137,20 @@ def test_tile_shapes(tl, tg):
     assert_all_stages(f.sparse, p, stages=(4, 5, 6, 7, 9), tag=f"tiles {tl}/{tg}")
 
 
+@pytest.mark.parametrize("tl", [0, 5, 6, 7])
+def test_sixteen_row_phase2_tiles(tl):
+    """Phase-2 tile id 8 (16 rows, the default chain only; stage hooks run
+    the general phase 2 on 32-row tiles), alone and in a batch."""
+    p = api.Params(tile_local=tl, tile_global=8)
+    f = synth.lidar_frame(133, 290, seed=[13, tl], n_rows=40, density=0.05)
+    print(f"[tiles] local {tl} global 8", flush=True)
+    assert_all_stages(f.sparse, p, stages=(4, 5, 6, 7, 9), tag=f"tiles {tl}/8")
+    frames = [torch.from_numpy(synth.lidar_frame(H, W, seed=[13, tl, H], n_rows=min(64, H), density=0.05).sparse)
+              .to(DEV) for H, W in [(133, 290), (375, 1242), (17, 40)]]
+    for t, o in zip(frames, api.complete_batch(frames, p)):
+        assert np.array_equal(bits(o.cpu().numpy()), bits(api.complete(t).cpu().numpy()))
+
+
 @pytest.mark.parametrize("sigma", [0.8, 1.1, 2.0])
 def test_gaussian_sigma_tolerance(sigma):
     p = api.Params(gauss_sigma=sigma)
