@@ -81,11 +81,16 @@ class GraphBatch:
         params = params or Params()
         # as the library does for calls that see their frames: 32-row
         # phase-1 tiles when 64-row ones would give the GPU fewer waves than
-        # it has SIMDs, and 16-row phase-2 tiles (the default chain only) when
-        # 32-row ones would (the plan and the captured launch share them)
+        # it has SIMDs, 16-row ones when 32-row ones would too, and 16-row
+        # phase-2 tiles (the default chain only) when 32-row ones would (the
+        # plan and the captured launch share them); only tiles the chain
+        # supports
         lt64, gt32, _ = _tile_counts(params.to_c(), self.capacity)
         if params.tile_local == 0 and lt64 < AUTO_TILE_WAVES:
-            params = dataclasses.replace(params, tile_local=7)
+            lt32, _, _ = _tile_counts(dataclasses.replace(params, tile_local=7).to_c(), self.capacity)
+            small = dataclasses.replace(params, tile_local=8 if lt32 < AUTO_TILE_WAVES else 7)
+            if _placeholder_bytes(self.capacity, small) > 0:
+                params = small
         if params.tile_global == 0 and gt32 < AUTO_TILE_WAVES:
             small = dataclasses.replace(params, tile_global=8)
             if _placeholder_bytes(self.capacity, small) > 0:

@@ -39,7 +39,7 @@ struct Resolved {
   bool lstream, gstream;   // streaming kernels (tile ids 5-7) or LDS tile kernels (ids 1-4)
 };
 
-constexpr int kTileIdsLocal = 7;
+constexpr int kTileIdsLocal = 8;
 constexpr int kTileIdsGlobal = 8;   // id 8: 16-row streaming tiles, default chain only
 
 bool odd_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v % 2) == 1; }
@@ -139,20 +139,23 @@ int resolve(const ipb_params* p, Resolved* r) {
 
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// The default tiles for calls that know their frames: 32-row phase-1 tiles
-// when 64-row ones would give the GPU fewer waves than its SIMDs can hold
-// one each of (1024 on MI355X), and for the default chain 16-row phase-2
-// tiles when 32-row ones would, so that small launches (one frame) spread
-// over more waves.  Calls that only see a plan keep the defaults, as the
-// plan was built with them.
+// The default tiles for calls that know their frames, so that small
+// launches (one frame) spread over more waves: when 64-row phase-1 tiles
+// would give the GPU fewer waves than its SIMDs can hold one each of (1024
+// on MI355X), 32-row ones, or 16-row ones when 32-row ones would too; and for
+// the default chain 16-row phase-2 tiles when 32-row ones would.  Calls that
+// only see a plan keep the defaults, as the plan was built with them.
+// count(rows, cols): the launch's tiles of that shape.
 constexpr long long kAutoTileWaves = 1024;
-void auto_tiles(const ipb_params* p, Resolved* r, long long tiles_local, long long tiles_global) {
-  if (p->tile_local == 0 && r->lstream && r->ltile == 5 && tiles_local < kAutoTileWaves) {
-    r->ltile = 7;
-    r->lth = stream_local_tile_rows(7);
-    r->ltw = stream_local_tile_cols(7);
+template <class Count>
+void auto_tiles(const ipb_params* p, Resolved* r, Count count) {
+  if (p->tile_local == 0 && r->lstream && r->ltile == 5 && count(r->lth, r->ltw) < kAutoTileWaves) {
+    const int id = count(stream_local_tile_rows(7), stream_local_tile_cols(7)) < kAutoTileWaves ? 8 : 7;
+    r->ltile = id;
+    r->lth = stream_local_tile_rows(id);
+    r->ltw = stream_local_tile_cols(id);
   }
-  if (p->tile_global == 0 && r->gstream && r->gtile == 6 && tiles_global < kAutoTileWaves && r->lstream &&
+  if (p->tile_global == 0 && r->gstream && r->gtile == 6 && count(r->gth, r->gtw) < kAutoTileWaves && r->lstream &&
       fast_chain(r->kp)) {
     r->gtile = 8;
     r->gth = stream_global_tile_rows(8);
@@ -163,20 +166,19 @@ void auto_tiles(const ipb_params* p, Resolved* r, long long tiles_local, long lo
 int resolve_single(const ipb_params* p, int H, int W, Resolved* r) {
   const int st = resolve(p, r);
   if (st == IPB_OK && size_ok(H, W))
-    auto_tiles(p, r, (long long)cdiv(W, r->ltw) * cdiv(H, r->lth), (long long)cdiv(W, r->gtw) * cdiv(H, r->gth));
+    auto_tiles(p, r, [&](int th, int tw) { return (long long)cdiv(W, tw) * cdiv(H, th); });
   return st;
 }
 
 int resolve_frames(const ipb_params* p, const ipb_frame* frames, int n, Resolved* r) {
   const int st = resolve(p, r);
   if (st != IPB_OK || frames == nullptr || n < 1) return st;
-  long long tl = 0, tg = 0;
-  for (int i = 0; i < n; ++i)
-    if (size_ok(frames[i].H, frames[i].W)) {
-      tl += (long long)cdiv(frames[i].W, r->ltw) * cdiv(frames[i].H, r->lth);
-      tg += (long long)cdiv(frames[i].W, r->gtw) * cdiv(frames[i].H, r->gth);
-    }
-  auto_tiles(p, r, tl, tg);
+  auto_tiles(p, r, [&](int th, int tw) {
+    long long t = 0;
+    for (int i = 0; i < n; ++i)
+      if (size_ok(frames[i].H, frames[i].W)) t += (long long)cdiv(frames[i].W, tw) * cdiv(frames[i].H, th);
+    return t;
+  });
   return st;
 }
 

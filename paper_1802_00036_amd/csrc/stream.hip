@@ -65,6 +65,15 @@ __device__ __forceinline__ int ldk(gcint* row, unsigned off) { return *(gcint*)(
 __device__ __forceinline__ float ldf(gcfloat* row, unsigned off) { return *(gcfloat*)((gcchar*)row + off); }
 __device__ __forceinline__ void stk(gint* row, unsigned off, int v) { *(gint*)((gchar*)row + off) = v; }
 __device__ __forceinline__ float val(int k) { return __int_as_float(k); }
+// Device-memory atomic min as a global (not flat) atomic.  A flat operation
+// still in flight makes every later wait for a vector load a wait for all
+// outstanding loads, which would drain the row prefetch of the next tile.
+__device__ __forceinline__ void atomic_min_g(int* p, int v) {
+  __hip_atomic_fetch_min((gint*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int atomic_add_g(int* p, int v) {
+  return __hip_atomic_fetch_add((gint*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 // lane i receives lane i-1's value (lane 0 receives 0; its neighbours are
 // outside the tile's input columns and never feed an output)
 __device__ __forceinline__ int from_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
@@ -111,6 +120,10 @@ __device__ __forceinline__ P* uni_ptr(P* p) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
   const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
   return reinterpret_cast<P*>(((unsigned long long)hi << 32) | lo);
+}
+// Descriptor fidx of a device plan.
+__device__ __forceinline__ FrameDesc plan_frame(const FrameSource& src, int fidx) {
+  return reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx];
 }
 __device__ __forceinline__ FrameDesc uniform_frame(const FrameDesc& f) {
   FrameDesc u;
@@ -348,8 +361,8 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       stk(dst, (o4row && outb) ? ro + ub : sink, ob);
     }
   }
-  if (outa && first_a != kNoTop) atomicMin(f.top + ca, first_a);
-  if (outb && first_b != kNoTop) atomicMin(f.top + cb, first_b);
+  if (outa && first_a != kNoTop) atomic_min_g(f.top + ca, first_a);
+  if (outb && first_b != kNoTop) atomic_min_g(f.top + cb, first_b);
   if (outa) stk((gint*)rec, ua, (int)(holes_a | record_first(first_a, ty0)));
   if (outb) stk((gint*)rec, ub, (int)(holes_b | record_first(first_b, ty0)));
 }
@@ -360,7 +373,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(5))) voi
   const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
   for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
     FrameDesc f;
-    if (src.plan) f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[src.plan->ltab[t]];
+    if (src.plan) f = plan_frame(src, gc(src.plan->ltab)[t]);
     else f = src.single;
     f = uniform_frame(f);
     const int lt = t - f.ltile0;
@@ -418,8 +431,8 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
   const bool median = kp.rm == 2;
   if (!PATCHED && (H < 3 || W < 3)) {   // reflect-101 on tiny frames: leave it to the LDS kernel
     if (lane == 0) {
-      const int pos = atomicAdd(slow + 1, 1);
-      if (pos < cap) slow[lds_queue_offset(cap) + pos] = t;
+      const int pos = atomic_add_g(slow + 1, 1);
+      if (pos < cap) gw(slow)[lds_queue_offset(cap) + pos] = t;
     }
     return;
   }
@@ -696,9 +709,9 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
     }
     int ps = 0, pd = 0, pc = 0;
     if (lane == 0) {
-      if (smask) ps = atomicAdd(slow + 0, __popc(smask));
-      if (dmask) pd = atomicAdd(slow + 2, __popc(dmask));
-      if (ncell) pc = atomicAdd(slow + 3, ncell);
+      if (smask) ps = atomic_add_g(slow + 0, __popc(smask));
+      if (dmask) pd = atomic_add_g(slow + 2, __popc(dmask));
+      if (ncell) pc = atomic_add_g(slow + 3, ncell);
     }
     ps = __shfl(ps, 0);
     pd = __shfl(pd, 0);
@@ -710,12 +723,12 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
       const bool dense = (dmask >> lane) & 1u;
       const int pos = dense ? pd + __popc(dmask & below) : ps + __popc(smask & below);
       if (pos < 4 * cap) {
-        int32_t* e = slow + (dense ? dense_queue_offset(cap) : sparse_queue_offset(cap)) + 2 * pos;
+        gint* e = gw(slow) + (dense ? dense_queue_offset(cap) : sparse_queue_offset(cap)) + 2 * pos;
         e[0] = fidx;
         e[1] = gt | (lane << 27);
       }
     }
-    int32_t* cells = slow + cell_queue_offset(cap);
+    gint* cells = gw(slow) + cell_queue_offset(cap);
 #pragma unroll
     for (int qk = 0; qk < 4; ++qk) {
       if (((smask >> qk) & 1u) == 0) continue;
@@ -741,8 +754,8 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) voi
     FrameDesc f;
     int fidx = 0;
     if (src.plan) {
-      fidx = src.plan->gtab[t];
-      f = reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx];
+      fidx = gc(src.plan->gtab)[t];
+      f = plan_frame(src, fidx);
     } else {
       f = src.single;
     }
@@ -801,13 +814,13 @@ __device__ __forceinline__ int window_max(const FrameDesc& f, const KParams& kp,
 
 __global__ __launch_bounds__(kLanes) void k_fill_cells(FrameSource src, KParams kp) {
   const int lane = threadIdx.x;
-  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  gcint* slow = gc(src.plan ? src.plan->slow : src.slow);
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int count = min(slow[3], 4 * kCellEmpty * cap);
-  const int32_t* cells = slow + cell_queue_offset(cap);
+  gcint* cells = slow + cell_queue_offset(cap);
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int fidx = cells[2 * i], pos = cells[2 * i + 1];
-    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
+    FrameDesc f = src.plan ? plan_frame(src, fidx) : src.single;
     f = uniform_frame(f);
     const int W = f.W;
     const int y = uni(pos / W), x = uni(pos - (pos / W) * W);
@@ -966,14 +979,14 @@ __global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, K
   __shared__ int S[SR * kDW];
   __shared__ int s_top[kDW];
   const int tid = threadIdx.x;
-  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  gcint* slow = gc(src.plan ? src.plan->slow : src.slow);
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int count = min(slow[2], 4 * cap);
-  const int32_t* queue = slow + dense_queue_offset(cap);
+  gcint* queue = slow + dense_queue_offset(cap);
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int fidx = queue[2 * i], tq = queue[2 * i + 1];
     const int gt = tq & ((1 << 27) - 1), qk = (unsigned)tq >> 27;
-    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
+    FrameDesc f = src.plan ? plan_frame(src, fidx) : src.single;
     f = uniform_frame(f);
     const int tr = gt / f.gcols;
     const int y0 = tr * TH + qk * QR, tx0 = (gt - tr * f.gcols) * kGlobalTW;
@@ -1029,25 +1042,26 @@ __device__ __forceinline__ unsigned wave_or(unsigned v) {
   return (unsigned)__builtin_amdgcn_readlane(x, 63);
 }
 
-// One wave per column of phase-1 tiles (the waves of the first tile row's
-// tiles) walks the records of every tile row, eight tile rows at a time, and
-// queues the 32-row bands of tiles that may hold such a cell: the launch
-// tile id, and the frame index with the band in bits 24..25.  Frames under 3 rows or columns are left to phase 2, which
+// One wave per column of phase-1 tiles and group of eight tile rows (the
+// waves of the group's first tile row) reads the records of those tiles
+// and queues the 32-row bands that may hold such a cell: the launch tile id,
+// and the frame index with the band in bits 24..25.  Frames under 3 rows or columns are left to phase 2, which
 // recomputes them whole.
 __global__ __launch_bounds__(kLanes) void k_fill_scan(FrameSource src, KParams kp, int lth) {
   const int lane = threadIdx.x;
   const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
   int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int gcap = src.plan ? src.plan->slow_cap : src.slow_cap;
-  int32_t* queue = slow + fill_queue_offset(gcap);
+  gint* queue = gw(slow + fill_queue_offset(gcap));
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    const int fidx = src.plan ? src.plan->ltab[t] : 0;
-    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
+    const int fidx = src.plan ? gc(src.plan->ltab)[t] : 0;
+    FrameDesc f = src.plan ? plan_frame(src, fidx) : src.single;
     f = uniform_frame(f);
     const int lt = t - f.ltile0;
     const int H = f.H, W = f.W;
-    if (lt >= f.lcols || H < 3 || W < 3) continue;
-    const int x0 = lt * kLocalTW;
+    const int tr0 = lt / f.lcols, tc = lt - tr0 * f.lcols;   // tile row and column
+    if ((tr0 & 7) != 0 || H < 3 || W < 3) continue;
+    const int x0 = tc * kLocalTW;
     const int xa = x0 + lane, xb = x0 + kLanes + lane;
     const bool ina = xa < W, inb = kLanes + lane < kLocalTW && xb < W;
     const int xac = min(xa, W - 1), xbc = min(xb, W - 1);
@@ -1055,35 +1069,33 @@ __global__ __launch_bounds__(kLanes) void k_fill_scan(FrameSource src, KParams k
     gcint* rec = gc(f.v6p);
     const int ta = top[xac], tb = top[xbc];
     const int ntr = (H + lth - 1) / lth;
-    for (int tr0 = 0; tr0 < ntr; tr0 += 8) {
-      int ra[8], rb[8];
+    int ra[8], rb[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const size_t row = (size_t)min(tr0 + k, ntr - 1) * W;
-        ra[k] = rec[row + xac];
-        rb[k] = rec[row + xbc];
-      }
-      // bands with candidates: four bits per tile row (bit 4 k + b: tile row
-      // tr0 + k, band b), or-ed over the tile columns of the wave
-      unsigned m = 0u;
+    for (int k = 0; k < 8; ++k) {
+      const size_t row = (size_t)min(tr0 + k, ntr - 1) * W;
+      ra[k] = rec[row + xac];
+      rb[k] = rec[row + xbc];
+    }
+    // bands with candidates: four bits per tile row (bit 4 k + b: tile row
+    // tr0 + k, band b), or-ed over the tile columns of the wave
+    unsigned m = 0u;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int y0 = (tr0 + k) * lth, rows = min(lth, H - y0);
-        if (tr0 + k < ntr) {
-          const unsigned mk = (ina ? record_bands(ra[k], ta, y0, rows, H) : 0u) |
-                              (inb ? record_bands(rb[k], tb, y0, rows, H) : 0u);
-          m |= mk << (4 * k);
-        }
+    for (int k = 0; k < 8; ++k) {
+      const int y0 = (tr0 + k) * lth, rows = min(lth, H - y0);
+      if (tr0 + k < ntr) {
+        const unsigned mk = (ina ? record_bands(ra[k], ta, y0, rows, H) : 0u) |
+                            (inb ? record_bands(rb[k], tb, y0, rows, H) : 0u);
+        m |= mk << (4 * k);
       }
-      const unsigned need = wave_or(m);
-      if (need == 0u) continue;
-      int pos = 0;
-      if (lane == 0) pos = atomicAdd(slow + 4, __popc(need));
-      pos = __shfl(pos, 0) + __popc(need & ((1u << (lane & 31)) - 1u));
-      if (lane < 32 && ((need >> lane) & 1u) && pos < kBandsPerTile * total) {
-        queue[2 * pos] = f.ltile0 + (tr0 + lane / 4) * f.lcols + lt;
-        queue[2 * pos + 1] = fidx | ((lane & 3) << 24);
-      }
+    }
+    const unsigned need = wave_or(m);
+    if (need == 0u) continue;   // the next tile
+    int pos = 0;
+    if (lane == 0) pos = atomic_add_g(slow + 4, __popc(need));
+    pos = __shfl(pos, 0) + __popc(need & ((1u << (lane & 31)) - 1u));
+    if (lane < 32 && ((need >> lane) & 1u) && pos < kBandsPerTile * total) {
+      queue[2 * pos] = f.ltile0 + (tr0 + lane / 4) * f.lcols + tc;
+      queue[2 * pos + 1] = fidx | ((lane & 3) << 24);
     }
   }
 }
@@ -1146,17 +1158,17 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
   __shared__ short s_hcol[kLocalTW], s_hfirst[kLocalTW];
   __shared__ int s_n, s_lead, s_nh, s_cand;
   const int tid = threadIdx.x, lane = tid & (kLanes - 1), wv = tid / kLanes;
-  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  gcint* slow = gc(src.plan ? src.plan->slow : src.slow);
   const int gcap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int lcap = src.plan ? src.plan->ltiles : src.single_ltiles;
   const int count = min(slow[4], kBandsPerTile * lcap);
-  const int32_t* queue = slow + fill_queue_offset(gcap);
+  gcint* queue = slow + fill_queue_offset(gcap);
   const int kthr = key(kp.thr);
   const int rl = kp.rl;
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int t = queue[2 * i], e1 = queue[2 * i + 1];
     const int fidx = e1 & 0xffffff, band = (unsigned)e1 >> 24;
-    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
+    FrameDesc f = src.plan ? plan_frame(src, fidx) : src.single;
     f = uniform_frame(f);
     const int H = f.H, W = f.W;
     const int lt = t - f.ltile0, tr = lt / f.lcols, tc = lt - tr * f.lcols;
@@ -1252,16 +1264,16 @@ template <int TH, bool FAST>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) void k_global_patched(FrameSource src, KParams kp) {
   constexpr int QR = TH / 4;
   const int lane = threadIdx.x;
-  const int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  gcint* slow = gc(src.plan ? src.plan->slow : src.slow);
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int n_sparse = min(slow[0], 4 * cap), count = n_sparse + min(slow[2], 4 * cap);
   if (kp.last_stage == 5) return;                   // the stage-5 map needs no second pass
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
-    const int32_t* e = i < n_sparse ? slow + sparse_queue_offset(cap) + 2 * i
-                                    : slow + dense_queue_offset(cap) + 2 * (i - n_sparse);
+    gcint* e = i < n_sparse ? slow + sparse_queue_offset(cap) + 2 * i
+                            : slow + dense_queue_offset(cap) + 2 * (i - n_sparse);
     const int fidx = e[0], tq = e[1];
     const int gt = tq & ((1 << 27) - 1), qk = (unsigned)tq >> 27;
-    FrameDesc f = src.plan ? reinterpret_cast<const FrameDesc*>(src.plan + 1)[fidx] : src.single;
+    FrameDesc f = src.plan ? plan_frame(src, fidx) : src.single;
     f = uniform_frame(f);
     const int tr = gt / f.gcols;
     global_stream_tile<QR, true, FAST>(f, kp, 0, fidx, gt, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane,
@@ -1269,7 +1281,9 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) voi
   }
 }
 
-constexpr int stream_local_rows(int id) { return id == 5 ? 64 : id == 6 ? 128 : id == 7 ? 32 : 0; }
+constexpr int stream_local_rows(int id) {
+  return id == 5 ? 64 : id == 6 ? 128 : id == 7 ? 32 : id == 8 ? 16 : 0;
+}
 constexpr int stream_global_rows(int id) {
   return id == 5 ? 64 : id == 6 ? 32 : id == 7 ? 128 : id == 8 ? 16 : 0;
 }
@@ -1298,7 +1312,8 @@ bool stream_global_supported(int rm, int rg) { return (rm == 0 || rm == 2) && rg
 
 #define IPB_STREAM_LOCAL(X)                                                          \
   X(2, 2, 5) X(1, 2, 5) X(0, 2, 5) X(3, 2, 5) X(0, 1, 5) X(0, 3, 5) X(2, 2, 6) X(2, 2, 7) \
-  X(1, 2, 6) X(0, 2, 6) X(3, 2, 6) X(0, 1, 6) X(0, 3, 6) X(1, 2, 7) X(0, 2, 7) X(3, 2, 7) X(0, 1, 7) X(0, 3, 7)
+  X(1, 2, 6) X(0, 2, 6) X(3, 2, 6) X(0, 1, 6) X(0, 3, 6) X(1, 2, 7) X(0, 2, 7) X(3, 2, 7) X(0, 1, 7) X(0, 3, 7) \
+  X(2, 2, 8) X(1, 2, 8) X(0, 2, 8) X(3, 2, 8) X(0, 1, 8) X(0, 3, 8)
 
 hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
 #define X(S, R, ID)                                                                                        \
@@ -1320,7 +1335,8 @@ hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int t
   if (tile_id == 5) { IPB_GS(64) }
   else if (tile_id == 6) { IPB_GS(32) }
   else if (tile_id == 7) { IPB_GS(128) }
-  else if (tile_id == 8) { IPB_GS(16) }
+  else if (tile_id == 8 && fast)   // 16-row tiles: the default chain only
+    hipLaunchKernelGGL((k_global_stream<16, true>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else return hipErrorInvalidValue;
 #undef IPB_GS
   return hipGetLastError();
@@ -1383,7 +1399,7 @@ int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast)
   if (tile_id == 5) return fast ? occupancy_s(k_global_stream<64, true>) : occupancy_s(k_global_stream<64, false>);
   if (tile_id == 6) return fast ? occupancy_s(k_global_stream<32, true>) : occupancy_s(k_global_stream<32, false>);
   if (tile_id == 7) return fast ? occupancy_s(k_global_stream<128, true>) : occupancy_s(k_global_stream<128, false>);
-  if (tile_id == 8) return fast ? occupancy_s(k_global_stream<16, true>) : occupancy_s(k_global_stream<16, false>);
+  if (tile_id == 8 && fast) return occupancy_s(k_global_stream<16, true>);
   return 1;
 }
 

@@ -167,11 +167,15 @@ def test_sixteen_row_phase2_tiles_and_their_automatic_use():
     assert ws(352, 1216, tile_global=8) > 0
     assert ws(352, 1216, tile_global=8, median_size=3) == 0            # not the default chain
     assert ws(352, 1216, tile_global=8, tile_local=1) == 0             # LDS phase 1: not the default chain
-    # one 352x1216 frame: 11 x 11 phase-2 tiles of 32 rows, so the automatic choice is 16 rows
-    assert ws(352, 1216) == ws(352, 1216, tile_local=7, tile_global=8)
-    # one 1024x4096 frame: 32 x 35 = 1120 phase-2 tiles of 32 rows, so 32 rows stay
+    # one 352x1216 frame: 11 x 11 phase-2 tiles of 32 rows and 11 x 12
+    # phase-1 tiles of 32 rows, so the automatic choice is 16 rows for both
+    assert ws(352, 1216) == ws(352, 1216, tile_local=8, tile_global=8)
+    assert ws(352, 1216) != ws(352, 1216, tile_local=7, tile_global=8)
+    # one 1024x4096 frame: 32 x 35 = 1120 phase-2 tiles and 32 x 38 = 1216
+    # phase-1 tiles of 32 rows, so 32 rows stay for both
     assert ws(1024, 4096) == ws(1024, 4096, tile_local=7, tile_global=6)
     assert ws(1024, 4096) != ws(1024, 4096, tile_local=7, tile_global=8)
+    assert ws(1024, 4096) != ws(1024, 4096, tile_local=8, tile_global=6)
 
 
 def test_tile_table():

@@ -6,6 +6,8 @@ same exact value once).  For sigma > 0 the blur taps are not dyadic, the sums
 are not exact and the order differs (separable on the GPU, 2-D in the
 oracle): stage 8 must then agree within 1e-5 relative and the output within
 1e-5 * v8 + one ulp of the output (output = max_depth - v8)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -128,7 +130,7 @@ def test_param_variants(i):
     assert_all_stages(synth.random_map(rng, 37, 70, 0.03, 1.0, 79.0), p, tag=f"variant {i} random")
 
 
-@pytest.mark.parametrize("tl", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tl", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("tg", [1, 4, 5, 6, 7])
 def test_tile_shapes(tl, tg):
     p = api.Params(tile_local=tl, tile_global=tg)
@@ -137,7 +139,22 @@ def test_tile_shapes(tl, tg):
     assert_all_stages(f.sparse, p, stages=(4, 5, 6, 7, 9), tag=f"tiles {tl}/{tg}")
 
 
-@pytest.mark.parametrize("tl", [0, 5, 6, 7])
+@pytest.mark.parametrize("i", range(8))
+def test_sixteen_row_phase1_tiles_every_dilation(i):
+    """Phase-1 tile id 8 (16 rows: one record band per tile) with each
+    dilation the streaming phase 1 serves, on frames spanning several tile
+    rows and a ragged last one."""
+    p = dataclasses.replace(VARIANTS[i], tile_local=8)
+    if api.workspace_bytes(150, 300, p) == 0:
+        # a chain the streaming phase 1 does not serve, at any tile height
+        assert api.workspace_bytes(150, 300, dataclasses.replace(p, tile_local=5)) == 0
+        return
+    f = synth.lidar_frame(150, 300, seed=[14, i], n_rows=32, density=0.05)
+    print(f"[tiles] local 8, variant {i}", flush=True)
+    assert_all_stages(f.sparse, p, tag=f"local 8 variant {i}")
+
+
+@pytest.mark.parametrize("tl", [0, 5, 6, 7, 8])
 def test_sixteen_row_phase2_tiles(tl):
     """Phase-2 tile id 8 (16 rows, the default chain only; stage hooks run
     the general phase 2 on 32-row tiles), alone and in a batch."""
