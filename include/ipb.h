@@ -108,11 +108,12 @@ void ipb_params_default(ipb_params* p);
  * large-fill values of cells left empty after the extension (its start also
  * holds the phase-1 column records), one int32 per column and the queues of
  * the tiles, bands and cells that need the large fill.  With tile_local 0 a
- * frame too small to give the GPU a wave per SIMD (1024 waves) with 64-row
- * phase-1 tiles takes 32-row ones, or 16-row ones if 32-row ones are too
- * few as well; with tile_global 0 and the default chain (stages 1-4 and 5-9
- * on the streaming kernels, 5x5 median) one too small to do so with 32-row
- * phase-2 tiles takes 16-row ones, here and in the calls below.
+ * frame whose 64-row phase-1 tiles give the GPU fewer than two waves per
+ * SIMD (2048 waves) takes 32-row ones, or 16-row ones if those give fewer
+ * than one (1024); with tile_global 0 and the default chain (stages 1-4 and
+ * 5-9 on the streaming kernels, 5x5 median) one whose 32-row phase-2 tiles
+ * give fewer than four (4096) takes 16-row ones, here and in the calls
+ * below.
  * Returns 0 for invalid sizes or parameters. */
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p);
 

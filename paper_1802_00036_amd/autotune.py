@@ -207,10 +207,13 @@ def candidate_ids(phase: int) -> List[int]:
 
 
 def tune(frames: Sequence[torch.Tensor], params: Optional[Params] = None, reps: int = 5,
-         use_cache: bool = True, report: Optional[list] = None, streams: int = 1) -> Params:
+         use_cache: bool = True, report: Optional[list] = None, streams: int = 1,
+         use_shipped: bool = True) -> Params:
     """Parameters with the fastest tile shapes for batches like `frames`
     (outputs and results are unchanged by the choice), run one at a time
-    (streams = 1) or `streams` batches in flight on as many streams."""
+    (streams = 1) or `streams` batches in flight on as many streams.
+    use_cache: read (and write) the user cache; use_shipped: also read the
+    package's table when the user cache has no entry."""
     p0 = params or Params()
     frames = list(frames)
     if not frames:
@@ -221,7 +224,7 @@ def tune(frames: Sequence[torch.Tensor], params: Optional[Params] = None, reps: 
         key += f"|streams{streams}"
     path = cache_path()
     if use_cache:
-        hit = _load_cache(path).get(key) or _load_cache(SHIPPED_TABLE).get(key)
+        hit = _load_cache(path).get(key) or (_load_cache(SHIPPED_TABLE).get(key) if use_shipped else None)
         if hit:
             return dataclasses.replace(p0, tile_local=int(hit["tile_local"]), tile_global=int(hit["tile_global"]))
     stream = torch.cuda.Stream(device=frames[0].device)
@@ -281,14 +284,15 @@ def _write_table(path: str, streams: int, reps: int) -> None:
         p0 = Params(max_depth=140.0) if cfg == 4 else Params()
         os.environ["IPB_TUNE_CACHE"] = path + ".tmp"
         report: list = []
-        tuned = tune(frames, p0, reps=reps, use_cache=True, report=report, streams=streams)
+        tuned = tune(frames, p0, reps=reps, use_cache=True, report=report, streams=streams, use_shipped=False)
         for r in report:
             print(f"  {r['phase']}: tile {r['tile']}: {r['us']} us", flush=True)
         entries = _load_cache(path + ".tmp")
         table.update(entries)
         print(f"workload {cfg}: tiles {tuned.tile_local}/{tuned.tile_global}", flush=True)
         del frames
-    os.remove(path + ".tmp")
+    if os.path.exists(path + ".tmp"):
+        os.remove(path + ".tmp")
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
 

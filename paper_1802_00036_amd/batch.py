@@ -25,7 +25,8 @@ from . import _lib as L
 from .api import Params, _check_map, _stream_handle, _workspace, frames_array
 
 Shape = Tuple[int, int]
-AUTO_TILE_WAVES = 1024   # 256 CUs x 4 SIMDs
+# the library's automatic tile rule, in waves (MI355X: 256 CUs x 4 SIMDs)
+AUTO_LOCAL32, AUTO_LOCAL16, AUTO_GLOBAL16 = 2048, 1024, 4096
 
 
 def _tile_counts(p: L.CParams, shapes: Sequence[Shape]) -> Tuple[int, int, int]:
@@ -80,18 +81,18 @@ class GraphBatch:
         self.capacity = [tuple(int(v) for v in s) for s in capacity]
         params = params or Params()
         # as the library does for calls that see their frames: 32-row
-        # phase-1 tiles when 64-row ones would give the GPU fewer waves than
-        # it has SIMDs, 16-row ones when 32-row ones would too, and 16-row
-        # phase-2 tiles (the default chain only) when 32-row ones would (the
-        # plan and the captured launch share them); only tiles the chain
-        # supports
+        # phase-1 tiles when 64-row ones would give the GPU fewer than two
+        # waves per SIMD, 16-row ones when 32-row ones would give fewer than
+        # one, and 16-row phase-2 tiles (the default chain only) when 32-row
+        # ones would give fewer than four (the plan and the captured launch
+        # share them); only tiles the chain supports
         lt64, gt32, _ = _tile_counts(params.to_c(), self.capacity)
-        if params.tile_local == 0 and lt64 < AUTO_TILE_WAVES:
+        if params.tile_local == 0 and lt64 < AUTO_LOCAL32:
             lt32, _, _ = _tile_counts(dataclasses.replace(params, tile_local=7).to_c(), self.capacity)
-            small = dataclasses.replace(params, tile_local=8 if lt32 < AUTO_TILE_WAVES else 7)
+            small = dataclasses.replace(params, tile_local=8 if lt32 < AUTO_LOCAL16 else 7)
             if _placeholder_bytes(self.capacity, small) > 0:
                 params = small
-        if params.tile_global == 0 and gt32 < AUTO_TILE_WAVES:
+        if params.tile_global == 0 and gt32 < AUTO_GLOBAL16:
             small = dataclasses.replace(params, tile_global=8)
             if _placeholder_bytes(self.capacity, small) > 0:
                 params = small

@@ -140,22 +140,24 @@ int resolve(const ipb_params* p, Resolved* r) {
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // The default tiles for calls that know their frames, so that small
-// launches (one frame) spread over more waves: when 64-row phase-1 tiles
-// would give the GPU fewer waves than its SIMDs can hold one each of (1024
-// on MI355X), 32-row ones, or 16-row ones when 32-row ones would too; and for
-// the default chain 16-row phase-2 tiles when 32-row ones would.  Calls that
-// only see a plan keep the defaults, as the plan was built with them.
+// launches spread over more waves, in waves per SIMD of the GPU (1024 SIMDs
+// on MI355X): 32-row phase-1 tiles when 64-row ones would give fewer than
+// two, 16-row ones when 32-row ones would give fewer than one; for the
+// default chain, 16-row phase-2 tiles when 32-row ones would give fewer than
+// four.  (Measured on MI355X on batches of 1-16 frames: below these sizes
+// the shorter tiles finish sooner despite their larger halo share.)  Calls
+// that only see a plan keep the defaults, as the plan was built with them.
 // count(rows, cols): the launch's tiles of that shape.
-constexpr long long kAutoTileWaves = 1024;
+constexpr long long kAutoLocal32 = 2048, kAutoLocal16 = 1024, kAutoGlobal16 = 4096;
 template <class Count>
 void auto_tiles(const ipb_params* p, Resolved* r, Count count) {
-  if (p->tile_local == 0 && r->lstream && r->ltile == 5 && count(r->lth, r->ltw) < kAutoTileWaves) {
-    const int id = count(stream_local_tile_rows(7), stream_local_tile_cols(7)) < kAutoTileWaves ? 8 : 7;
+  if (p->tile_local == 0 && r->lstream && r->ltile == 5 && count(r->lth, r->ltw) < kAutoLocal32) {
+    const int id = count(stream_local_tile_rows(7), stream_local_tile_cols(7)) < kAutoLocal16 ? 8 : 7;
     r->ltile = id;
     r->lth = stream_local_tile_rows(id);
     r->ltw = stream_local_tile_cols(id);
   }
-  if (p->tile_global == 0 && r->gstream && r->gtile == 6 && count(r->gth, r->gtw) < kAutoTileWaves && r->lstream &&
+  if (p->tile_global == 0 && r->gstream && r->gtile == 6 && count(r->gth, r->gtw) < kAutoGlobal16 && r->lstream &&
       fast_chain(r->kp)) {
     r->gtile = 8;
     r->gth = stream_global_tile_rows(8);

@@ -160,8 +160,9 @@ def test_batch_plan_layout():
 
 def test_sixteen_row_phase2_tiles_and_their_automatic_use():
     """Phase-2 tile id 8 (16 rows) serves the default chain only, and calls
-    that see their frames take it (with 32-row phase-1 tiles) when 32-row
-    phase-2 tiles would give the GPU fewer than 1024 waves."""
+    that see their frames take it when 32-row phase-2 tiles would give the
+    GPU fewer than 4096 waves; phase-1 tiles go to 32 rows under 2048 waves
+    of 64 rows, and to 16 rows under 1024 waves of 32 rows."""
     lib = L.lib()
     ws = lambda H, W, **kw: int(lib.ipb_workspace_bytes(H, W, ctypes.byref(P(**kw))))
     assert ws(352, 1216, tile_global=8) > 0
@@ -171,11 +172,12 @@ def test_sixteen_row_phase2_tiles_and_their_automatic_use():
     # phase-1 tiles of 32 rows, so the automatic choice is 16 rows for both
     assert ws(352, 1216) == ws(352, 1216, tile_local=8, tile_global=8)
     assert ws(352, 1216) != ws(352, 1216, tile_local=7, tile_global=8)
-    # one 1024x4096 frame: 32 x 35 = 1120 phase-2 tiles and 32 x 38 = 1216
-    # phase-1 tiles of 32 rows, so 32 rows stay for both
-    assert ws(1024, 4096) == ws(1024, 4096, tile_local=7, tile_global=6)
-    assert ws(1024, 4096) != ws(1024, 4096, tile_local=7, tile_global=8)
-    assert ws(1024, 4096) != ws(1024, 4096, tile_local=8, tile_global=6)
+    # one 1024x4096 frame: 16 x 38 = 608 phase-1 tiles of 64 rows but
+    # 32 x 38 = 1216 of 32 rows, so 32; 32 x 35 = 1120 phase-2 tiles of 32
+    # rows, under 4096, so 16
+    assert ws(1024, 4096) == ws(1024, 4096, tile_local=7, tile_global=8)
+    assert ws(1024, 4096) != ws(1024, 4096, tile_local=8, tile_global=8)
+    assert ws(1024, 4096) != ws(1024, 4096, tile_local=7, tile_global=6)
 
 
 def test_tile_table():
