@@ -6,7 +6,9 @@ plan executes eagerly and captures the same work into a HIP graph: a copy of
 the pinned plan into device memory, then every kernel of the chain with grids
 derived from the capacity (ipb_complete_planned).  Later runs only rewrite the
 pinned plan (frame pointers and sizes) and replay the graph, so any batch
-within the capacity is one graph launch.  The two pinned plans alternate: the
+within the capacity is one graph launch.  The graph leaves out the launch step
+for frames under 3 rows or columns; a batch that holds such a frame runs
+eagerly with every step instead.  The two pinned plans alternate: the
 host rewrites a plan only after the replay that last read it has finished,
 so batch k+1 can be queued while batch k runs.
 
@@ -124,9 +126,9 @@ class GraphBatch:
             return False
         return shapes_workspace_bytes(shapes, self.params) <= self.ws_bytes
 
-    def _enqueue(self, k: int) -> None:
+    def _enqueue(self, k: int, phase: int) -> None:
         self.plan_dev.copy_(self.plan_host[k], non_blocking=True)
-        st = L.lib().ipb_complete_planned(ctypes.c_void_p(self.plan_dev.data_ptr()), ctypes.byref(self.cp), -1,
+        st = L.lib().ipb_complete_planned(ctypes.c_void_p(self.plan_dev.data_ptr()), ctypes.byref(self.cp), phase,
                                           self.max_lt, self.max_gt, self.max_cols,
                                           _stream_handle(torch.cuda.current_stream()))
         L.check(st, "ipb_complete_planned")
@@ -157,14 +159,18 @@ class GraphBatch:
                                         ctypes.byref(gt), ctypes.byref(cols)), "ipb_plan_totals")
         if lt.value > self.max_lt or gt.value > self.max_gt or cols.value > self.max_cols:
             raise ValueError("batch exceeds the tile or column totals of the capacity")
+        # the captured launch leaves out the step for frames under 3 rows or
+        # columns (planned phase -2); a batch holding such a frame runs
+        # eagerly with every step
+        tiny = any(f.shape[0] < 3 or f.shape[1] < 3 for f in frames)
         with torch.cuda.stream(self.stream):
-            if not self.use_graph:
-                self._enqueue(k)
+            if not self.use_graph or tiny:
+                self._enqueue(k, -1)
             elif self.graphs[k] is None:
-                self._enqueue(k)                 # first run: eager, then capture the same work
+                self._enqueue(k, -2)             # first run: eager, then capture the same work
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g, stream=self.stream):
-                    self._enqueue(k)
+                    self._enqueue(k, -2)
                 self.graphs[k] = g
             else:
                 self.graphs[k].replay()

@@ -11,6 +11,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle
+from paper_1802_00036_amd import _lib as L
 from paper_1802_00036_amd import api, autotune, batch, serve, synth
 
 pytestmark = pytest.mark.gpu
@@ -19,6 +20,10 @@ DEV = "cuda:0"
 
 def bits(t):
     return np.ascontiguousarray(t.detach().cpu().numpy()).view(np.uint32)
+
+
+def ntiles(phase):
+    return int(L.lib().ipb_tile_count(phase))
 
 
 def lidar(H, W, seed, density=0.05):
@@ -49,7 +54,17 @@ def test_graph_replays_match_eager_across_batches():
             want = api.complete(f)
             torch.cuda.synchronize()
             assert np.array_equal(bits(o), bits(want)), f"batch {b} frame {tuple(f.shape)}"
-    assert gb.replays >= 4
+    # each pinned plan's first run without a frame under 3 rows or columns
+    # captures its graph; later such runs replay it; batches with one run
+    # eagerly with every launch step
+    captured, want_replays = [False, False], 0
+    for b, frames in enumerate(batches):
+        if any(f.shape[0] < 3 or f.shape[1] < 3 for f in frames):
+            continue
+        if captured[b % 2]:
+            want_replays += 1
+        captured[b % 2] = True
+    assert gb.replays == want_replays and want_replays >= 2
     m = batches[1][0].cpu().numpy()
     assert np.array_equal(bits(torch.from_numpy(oracle.complete_map(m))), bits(api.complete(batches[1][0])))
 
@@ -81,7 +96,7 @@ def test_autotune_picks_a_valid_pair_and_results_do_not_change(tmp_path, monkeyp
     frames = [lidar(int(h), int(w), [22, i]) for i, (h, w) in enumerate([(256, 800), (300, 1100), (512, 2000)])]
     report = []
     p = autotune.tune(frames, reps=2, report=report)
-    assert 1 <= p.tile_local <= 7 and 1 <= p.tile_global <= 7
+    assert 1 <= p.tile_local <= ntiles(1) and 1 <= p.tile_global <= ntiles(2)
     assert any(r["us"] is not None for r in report)
     again = autotune.tune(frames, reps=2)              # from the cache
     assert (again.tile_local, again.tile_global) == (p.tile_local, p.tile_global)
@@ -98,7 +113,7 @@ def test_autotune_for_batches_in_flight(tmp_path, monkeypatch):
     frames = [lidar(int(h), int(w), [24, i]) for i, (h, w) in enumerate([(256, 800), (375, 1242), (300, 1100)])]
     report = []
     p = autotune.tune(frames, reps=2, report=report, streams=2)
-    assert 1 <= p.tile_local <= 7 and 1 <= p.tile_global <= 7
+    assert 1 <= p.tile_local <= ntiles(1) and 1 <= p.tile_global <= ntiles(2)
     pairs = [r for r in report if r["phase"] == "2 streams"]
     assert pairs and any(r["us"] is not None for r in pairs)
     assert f"{p.tile_local}/{p.tile_global}" in [r["tile"] for r in pairs]
