@@ -109,11 +109,11 @@ void ipb_params_default(ipb_params* p);
  * holds the phase-1 column records), one int32 per column and the queues of
  * the tiles, bands and cells that need the large fill.  With tile_local 0 a
  * frame whose 64-row phase-1 tiles give the GPU fewer than two waves per
- * SIMD (2048 waves) takes 32-row ones, or 16-row ones if those give fewer
- * than one (1024); with tile_global 0 and the default chain (stages 1-4 and
- * 5-9 on the streaming kernels, 5x5 median) one whose 32-row phase-2 tiles
- * give fewer than four (4096) takes 16-row ones, here and in the calls
- * below.
+ * SIMD (2048 waves) takes 32-row ones, 16-row ones if those give fewer than
+ * one (1024), 8-row ones if 16-row ones give fewer than half (512); with
+ * tile_global 0 and the default chain (stages 1-4 and 5-9 on the streaming
+ * kernels, 5x5 median) phase 2 takes the tallest of 32, 16 and 8 rows that
+ * gives at least four (4096), here and in the calls below.
  * Returns 0 for invalid sizes or parameters. */
 size_t ipb_workspace_bytes(int H, int W, const ipb_params* p);
 
@@ -216,8 +216,8 @@ int ipb_last_hip_error(void);
 
 /* Tile shapes (rows, cols) of a tile id for phase 1 (local) or 2 (global);
  * returns IPB_ERR_INVALID_ARG for an unknown id.  Id 0 = automatic.  Phase-2
- * id 8 (16-row streaming tiles) serves the default chain only; with any
- * other chain it is IPB_ERR_UNSUPPORTED. */
+ * ids 8 and 9 (16- and 8-row streaming tiles) serve the default chain only;
+ * with any other chain they are IPB_ERR_UNSUPPORTED. */
 int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols);
 
 /* Number of tile ids per phase (ids 1..count). */

@@ -28,7 +28,7 @@ from .api import Params, _check_map, _stream_handle, _workspace, frames_array
 
 Shape = Tuple[int, int]
 # the library's automatic tile rule, in waves (MI355X: 256 CUs x 4 SIMDs)
-AUTO_LOCAL32, AUTO_LOCAL16, AUTO_GLOBAL16 = 2048, 1024, 4096
+AUTO_LOCAL32, AUTO_LOCAL16, AUTO_LOCAL8, AUTO_GLOBAL = 2048, 1024, 512, 4096
 
 
 def _tile_counts(p: L.CParams, shapes: Sequence[Shape]) -> Tuple[int, int, int]:
@@ -82,20 +82,23 @@ class GraphBatch:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.capacity = [tuple(int(v) for v in s) for s in capacity]
         params = params or Params()
-        # as the library does for calls that see their frames: 32-row
-        # phase-1 tiles when 64-row ones would give the GPU fewer than two
-        # waves per SIMD, 16-row ones when 32-row ones would give fewer than
-        # one, and 16-row phase-2 tiles (the default chain only) when 32-row
-        # ones would give fewer than four (the plan and the captured launch
-        # share them); only tiles the chain supports
-        lt64, gt32, _ = _tile_counts(params.to_c(), self.capacity)
-        if params.tile_local == 0 and lt64 < AUTO_LOCAL32:
-            lt32, _, _ = _tile_counts(dataclasses.replace(params, tile_local=7).to_c(), self.capacity)
-            small = dataclasses.replace(params, tile_local=8 if lt32 < AUTO_LOCAL16 else 7)
+        # as the library does for calls that see their frames: phase-1 tiles
+        # of 32 rows when 64-row ones would give the GPU fewer than two waves
+        # per SIMD, of 16 rows when 32-row ones would give fewer than one, of
+        # 8 rows when 16-row ones would give fewer than half; phase-2 tiles
+        # (the default chain only) of the tallest of 32, 16 and 8 rows that
+        # gives at least four (the plan and the captured launch share them);
+        # only tiles the chain supports
+        def count(phase, tid):
+            p = dataclasses.replace(params, **{"tile_local" if phase == 1 else "tile_global": tid})
+            return _tile_counts(p.to_c(), self.capacity)[phase - 1]
+        if params.tile_local == 0 and count(1, 0) < AUTO_LOCAL32:
+            tid = 7 if count(1, 7) >= AUTO_LOCAL16 else 8 if count(1, 8) >= AUTO_LOCAL8 else 9
+            small = dataclasses.replace(params, tile_local=tid)
             if _placeholder_bytes(self.capacity, small) > 0:
                 params = small
-        if params.tile_global == 0 and gt32 < AUTO_GLOBAL16:
-            small = dataclasses.replace(params, tile_global=8)
+        if params.tile_global == 0 and count(2, 0) < AUTO_GLOBAL:
+            small = dataclasses.replace(params, tile_global=8 if count(2, 8) >= AUTO_GLOBAL else 9)
             if _placeholder_bytes(self.capacity, small) > 0:
                 params = small
         self.params = params

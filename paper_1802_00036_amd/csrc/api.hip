@@ -39,8 +39,8 @@ struct Resolved {
   bool lstream, gstream;   // streaming kernels (tile ids 5-7) or LDS tile kernels (ids 1-4)
 };
 
-constexpr int kTileIdsLocal = 8;
-constexpr int kTileIdsGlobal = 8;   // id 8: 16-row streaming tiles, default chain only
+constexpr int kTileIdsLocal = 9;
+constexpr int kTileIdsGlobal = 9;   // ids 8, 9: 16- and 8-row streaming tiles, default chain only
 
 bool odd_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v % 2) == 1; }
 
@@ -117,9 +117,9 @@ int resolve(const ipb_params* p, Resolved* r) {
   r->lstream = r->ltile >= 5;
   r->gstream = r->gtile >= 5;
   if ((r->lstream && !ls_ok) || (r->gstream && !gs_ok)) return IPB_ERR_UNSUPPORTED;
-  // 16-row phase-2 tiles exist for the default chain only (its phase 2 has
-  // no second pass, whose quarters would be 4 rows)
-  if (r->gtile == 8 && !(r->lstream && fast_chain(k))) return IPB_ERR_UNSUPPORTED;
+  // 16- and 8-row phase-2 tiles exist for the default chain only (its
+  // phase 2 has no second pass, whose quarters would be 4 or 2 rows)
+  if (r->gtile >= 8 && !(r->lstream && fast_chain(k))) return IPB_ERR_UNSUPPORTED;
   if (r->lstream) {
     r->lth = stream_local_tile_rows(r->ltile);
     r->ltw = stream_local_tile_cols(r->ltile);
@@ -141,27 +141,30 @@ int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // The default tiles for calls that know their frames, so that small
 // launches spread over more waves, in waves per SIMD of the GPU (1024 SIMDs
-// on MI355X): 32-row phase-1 tiles when 64-row ones would give fewer than
-// two, 16-row ones when 32-row ones would give fewer than one; for the
-// default chain, 16-row phase-2 tiles when 32-row ones would give fewer than
-// four.  (Measured on MI355X on batches of 1-16 frames: below these sizes
-// the shorter tiles finish sooner despite their larger halo share.)  Calls
-// that only see a plan keep the defaults, as the plan was built with them.
+// on MI355X): phase 1 takes 32-row tiles when 64-row ones would give fewer
+// than two, 16-row ones when 32-row ones would give fewer than one, 8-row
+// ones when 16-row ones would give fewer than half; phase 2 of the default
+// chain takes the tallest of 32, 16 and 8 rows that gives at least four.
+// (Measured on MI355X on batches of 1-16 frames: below these sizes the
+// shorter tiles finish sooner despite their larger halo share.)  Calls that
+// only see a plan keep the defaults, as the plan was built with them.
 // count(rows, cols): the launch's tiles of that shape.
-constexpr long long kAutoLocal32 = 2048, kAutoLocal16 = 1024, kAutoGlobal16 = 4096;
+constexpr long long kAutoLocal32 = 2048, kAutoLocal16 = 1024, kAutoLocal8 = 512, kAutoGlobal = 4096;
 template <class Count>
 void auto_tiles(const ipb_params* p, Resolved* r, Count count) {
   if (p->tile_local == 0 && r->lstream && r->ltile == 5 && count(r->lth, r->ltw) < kAutoLocal32) {
-    const int id = count(stream_local_tile_rows(7), stream_local_tile_cols(7)) < kAutoLocal16 ? 8 : 7;
+    auto local = [&](int id) { return count(stream_local_tile_rows(id), stream_local_tile_cols(id)); };
+    const int id = local(7) >= kAutoLocal16 ? 7 : local(8) >= kAutoLocal8 ? 8 : 9;
     r->ltile = id;
     r->lth = stream_local_tile_rows(id);
     r->ltw = stream_local_tile_cols(id);
   }
-  if (p->tile_global == 0 && r->gstream && r->gtile == 6 && count(r->gth, r->gtw) < kAutoGlobal16 && r->lstream &&
+  if (p->tile_global == 0 && r->gstream && r->gtile == 6 && count(r->gth, r->gtw) < kAutoGlobal && r->lstream &&
       fast_chain(r->kp)) {
-    r->gtile = 8;
-    r->gth = stream_global_tile_rows(8);
-    r->gtw = stream_global_tile_cols(8);
+    const int id = count(stream_global_tile_rows(8), stream_global_tile_cols(8)) >= kAutoGlobal ? 8 : 9;
+    r->gtile = id;
+    r->gth = stream_global_tile_rows(id);
+    r->gtw = stream_global_tile_cols(id);
   }
 }
 
@@ -468,7 +471,7 @@ int run_single(const float* in, int H, int W, const ipb_params* p, float* out, i
     r.lth = local_tile_rows(1);
     r.ltw = local_tile_cols(1);
   }
-  if (last_stage < 9 && r.gtile == 8) {  // stage hooks run the general phase 2, on 32-row tiles
+  if (last_stage < 9 && r.gtile >= 8) {  // stage hooks run the general phase 2, on 32-row tiles
     r.gtile = 6;                          // (fewer tiles than the workspace was sized for)
     r.gth = stream_global_tile_rows(6);
     r.gtw = stream_global_tile_cols(6);

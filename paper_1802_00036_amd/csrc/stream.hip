@@ -1282,10 +1282,10 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 constexpr int stream_local_rows(int id) {
-  return id == 5 ? 64 : id == 6 ? 128 : id == 7 ? 32 : id == 8 ? 16 : 0;
+  return id == 5 ? 64 : id == 6 ? 128 : id == 7 ? 32 : id == 8 ? 16 : id == 9 ? 8 : 0;
 }
 constexpr int stream_global_rows(int id) {
-  return id == 5 ? 64 : id == 6 ? 32 : id == 7 ? 128 : id == 8 ? 16 : 0;
+  return id == 5 ? 64 : id == 6 ? 32 : id == 7 ? 128 : id == 8 ? 16 : id == 9 ? 8 : 0;
 }
 
 template <class K>
@@ -1313,7 +1313,8 @@ bool stream_global_supported(int rm, int rg) { return (rm == 0 || rm == 2) && rg
 #define IPB_STREAM_LOCAL(X)                                                          \
   X(2, 2, 5) X(1, 2, 5) X(0, 2, 5) X(3, 2, 5) X(0, 1, 5) X(0, 3, 5) X(2, 2, 6) X(2, 2, 7) \
   X(1, 2, 6) X(0, 2, 6) X(3, 2, 6) X(0, 1, 6) X(0, 3, 6) X(1, 2, 7) X(0, 2, 7) X(3, 2, 7) X(0, 1, 7) X(0, 3, 7) \
-  X(2, 2, 8) X(1, 2, 8) X(0, 2, 8) X(3, 2, 8) X(0, 1, 8) X(0, 3, 8)
+  X(2, 2, 8) X(1, 2, 8) X(0, 2, 8) X(3, 2, 8) X(0, 1, 8) X(0, 3, 8) \
+  X(2, 2, 9) X(1, 2, 9) X(0, 2, 9) X(3, 2, 9) X(0, 1, 9) X(0, 3, 9)
 
 hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
 #define X(S, R, ID)                                                                                        \
@@ -1335,8 +1336,10 @@ hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int t
   if (tile_id == 5) { IPB_GS(64) }
   else if (tile_id == 6) { IPB_GS(32) }
   else if (tile_id == 7) { IPB_GS(128) }
-  else if (tile_id == 8 && fast)   // 16-row tiles: the default chain only
+  else if (tile_id == 8 && fast)   // 16- and 8-row tiles: the default chain only
     hipLaunchKernelGGL((k_global_stream<16, true>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 9 && fast)
+    hipLaunchKernelGGL((k_global_stream<8, true>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else return hipErrorInvalidValue;
 #undef IPB_GS
   return hipGetLastError();
@@ -1345,9 +1348,9 @@ hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int t
 hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, int cell_grid,
                                 hipStream_t s) {
   // the fill values of the queued cells and of the dense quarters, then the
-  // second pass over both quarter queues (16-row tiles: the default chain
-  // only, which has no second pass)
-  if (tile_id == 8) return hipErrorInvalidValue;
+  // second pass over both quarter queues (16- and 8-row tiles: the default
+  // chain only, which has no second pass)
+  if (tile_id == 8 || tile_id == 9) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_fill_cells, dim3(cell_grid), dim3(kLanes), 0, s, src, kp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1400,6 +1403,7 @@ int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast)
   if (tile_id == 6) return fast ? occupancy_s(k_global_stream<32, true>) : occupancy_s(k_global_stream<32, false>);
   if (tile_id == 7) return fast ? occupancy_s(k_global_stream<128, true>) : occupancy_s(k_global_stream<128, false>);
   if (tile_id == 8 && fast) return occupancy_s(k_global_stream<16, true>);
+  if (tile_id == 9 && fast) return occupancy_s(k_global_stream<8, true>);
   return 1;
 }
 

@@ -159,25 +159,31 @@ def test_batch_plan_layout():
 
 
 def test_sixteen_row_phase2_tiles_and_their_automatic_use():
-    """Phase-2 tile id 8 (16 rows) serves the default chain only, and calls
-    that see their frames take it when 32-row phase-2 tiles would give the
-    GPU fewer than 4096 waves; phase-1 tiles go to 32 rows under 2048 waves
-    of 64 rows, and to 16 rows under 1024 waves of 32 rows."""
+    """Phase-2 tile ids 8 and 9 (16 and 8 rows) serve the default chain only.
+    Calls that see their frames take the tallest phase-2 tiles (32, 16, 8
+    rows) that give the GPU at least 4096 waves; phase-1 tiles go to 32 rows
+    under 2048 waves of 64 rows, to 16 rows under 1024 waves of 32 rows, and
+    to 8 rows under 512 waves of 16 rows."""
     lib = L.lib()
     ws = lambda H, W, **kw: int(lib.ipb_workspace_bytes(H, W, ctypes.byref(P(**kw))))
     assert ws(352, 1216, tile_global=8) > 0
     assert ws(352, 1216, tile_global=8, median_size=3) == 0            # not the default chain
     assert ws(352, 1216, tile_global=8, tile_local=1) == 0             # LDS phase 1: not the default chain
-    # one 352x1216 frame: 11 x 11 phase-2 tiles of 32 rows and 11 x 12
-    # phase-1 tiles of 32 rows, so the automatic choice is 16 rows for both
-    assert ws(352, 1216) == ws(352, 1216, tile_local=8, tile_global=8)
-    assert ws(352, 1216) != ws(352, 1216, tile_local=7, tile_global=8)
+    assert ws(352, 1216, tile_global=9) > 0 and ws(352, 1216, tile_local=9) > 0
+    assert ws(352, 1216, tile_global=9, median_size=3) == 0
+    assert ws(352, 1216, tile_local=9, median_size=3) > 0               # phase-1 ids serve every streaming chain
+    # one 352x1216 frame: 22 x 12 = 264 phase-1 tiles of 16 rows (under
+    # 512) and 22 x 11 = 242 phase-2 tiles of 16 rows (under 4096), so the
+    # automatic choice is 8 rows for both
+    assert ws(352, 1216) == ws(352, 1216, tile_local=9, tile_global=9)
+    assert ws(352, 1216) != ws(352, 1216, tile_local=8, tile_global=9)
+    assert ws(352, 1216) != ws(352, 1216, tile_local=9, tile_global=8)
     # one 1024x4096 frame: 16 x 38 = 608 phase-1 tiles of 64 rows but
-    # 32 x 38 = 1216 of 32 rows, so 32; 32 x 35 = 1120 phase-2 tiles of 32
-    # rows, under 4096, so 16
-    assert ws(1024, 4096) == ws(1024, 4096, tile_local=7, tile_global=8)
-    assert ws(1024, 4096) != ws(1024, 4096, tile_local=8, tile_global=8)
-    assert ws(1024, 4096) != ws(1024, 4096, tile_local=7, tile_global=6)
+    # 32 x 38 = 1216 of 32 rows, so 32; 64 x 35 = 2240 phase-2 tiles of 16
+    # rows, under 4096, so 8
+    assert ws(1024, 4096) == ws(1024, 4096, tile_local=7, tile_global=9)
+    assert ws(1024, 4096) != ws(1024, 4096, tile_local=8, tile_global=9)
+    assert ws(1024, 4096) != ws(1024, 4096, tile_local=7, tile_global=8)
 
 
 def test_tile_table():

@@ -130,7 +130,7 @@ def test_param_variants(i):
     assert_all_stages(synth.random_map(rng, 37, 70, 0.03, 1.0, 79.0), p, tag=f"variant {i} random")
 
 
-@pytest.mark.parametrize("tl", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("tl", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("tg", [1, 4, 5, 6, 7])
 def test_tile_shapes(tl, tg):
     p = api.Params(tile_local=tl, tile_global=tg)
@@ -139,29 +139,32 @@ def test_tile_shapes(tl, tg):
     assert_all_stages(f.sparse, p, stages=(4, 5, 6, 7, 9), tag=f"tiles {tl}/{tg}")
 
 
+@pytest.mark.parametrize("tl", [8, 9])
 @pytest.mark.parametrize("i", range(8))
-def test_sixteen_row_phase1_tiles_every_dilation(i):
-    """Phase-1 tile id 8 (16 rows: one record band per tile) with each
-    dilation the streaming phase 1 serves, on frames spanning several tile
-    rows and a ragged last one."""
-    p = dataclasses.replace(VARIANTS[i], tile_local=8)
+def test_short_phase1_tiles_every_dilation(i, tl):
+    """Phase-1 tile ids 8 and 9 (16 and 8 rows: one record band per tile)
+    with each dilation the streaming phase 1 serves, on frames spanning
+    several tile rows and a ragged last one."""
+    p = dataclasses.replace(VARIANTS[i], tile_local=tl)
     if api.workspace_bytes(150, 300, p) == 0:
         # a chain the streaming phase 1 does not serve, at any tile height
         assert api.workspace_bytes(150, 300, dataclasses.replace(p, tile_local=5)) == 0
         return
     f = synth.lidar_frame(150, 300, seed=[14, i], n_rows=32, density=0.05)
-    print(f"[tiles] local 8, variant {i}", flush=True)
-    assert_all_stages(f.sparse, p, tag=f"local 8 variant {i}")
+    print(f"[tiles] local {tl}, variant {i}", flush=True)
+    assert_all_stages(f.sparse, p, tag=f"local {tl} variant {i}")
 
 
-@pytest.mark.parametrize("tl", [0, 5, 6, 7, 8])
-def test_sixteen_row_phase2_tiles(tl):
-    """Phase-2 tile id 8 (16 rows, the default chain only; stage hooks run
-    the general phase 2 on 32-row tiles), alone and in a batch."""
-    p = api.Params(tile_local=tl, tile_global=8)
+@pytest.mark.parametrize("tg", [8, 9])
+@pytest.mark.parametrize("tl", [0, 5, 6, 7, 8, 9])
+def test_short_phase2_tiles(tl, tg):
+    """Phase-2 tile ids 8 and 9 (16 and 8 rows, the default chain only;
+    stage hooks run the general phase 2 on 32-row tiles), alone and in a
+    batch."""
+    p = api.Params(tile_local=tl, tile_global=tg)
     f = synth.lidar_frame(133, 290, seed=[13, tl], n_rows=40, density=0.05)
-    print(f"[tiles] local {tl} global 8", flush=True)
-    assert_all_stages(f.sparse, p, stages=(4, 5, 6, 7, 9), tag=f"tiles {tl}/8")
+    print(f"[tiles] local {tl} global {tg}", flush=True)
+    assert_all_stages(f.sparse, p, stages=(4, 5, 6, 7, 9), tag=f"tiles {tl}/{tg}")
     frames = [torch.from_numpy(synth.lidar_frame(H, W, seed=[13, tl, H], n_rows=min(64, H), density=0.05).sparse)
               .to(DEV) for H, W in [(133, 290), (375, 1242), (17, 40)]]
     for t, o in zip(frames, api.complete_batch(frames, p)):
