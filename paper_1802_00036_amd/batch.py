@@ -66,6 +66,29 @@ def shapes_workspace_bytes(shapes: Sequence[Shape], params: Optional[Params] = N
     return nb
 
 
+def auto_tiles(params: Params, shapes: Sequence[Shape]) -> Params:
+    """The tiles the library picks for a call that sees frames of these
+    shapes, as explicit ids (tile id 0 only): phase-1 tiles of 32 rows when
+    64-row ones would give the GPU fewer than two waves per SIMD, of 16 rows
+    when 32-row ones would give fewer than one, of 8 rows when 16-row ones
+    would give fewer than half; phase-2 tiles (the default chain only) of the
+    tallest of 32, 16 and 8 rows that gives at least four.  Only tiles the
+    chain supports."""
+    def count(p: Params, phase: int, tid: int) -> int:
+        q = dataclasses.replace(p, **{"tile_local" if phase == 1 else "tile_global": tid})
+        return _tile_counts(q.to_c(), shapes)[phase - 1]
+    if params.tile_local == 0 and count(params, 1, 0) < AUTO_LOCAL32:
+        tid = 7 if count(params, 1, 7) >= AUTO_LOCAL16 else 8 if count(params, 1, 8) >= AUTO_LOCAL8 else 9
+        small = dataclasses.replace(params, tile_local=tid)
+        if _placeholder_bytes(shapes, small) > 0:
+            params = small
+    if params.tile_global == 0 and count(params, 2, 0) < AUTO_GLOBAL:
+        small = dataclasses.replace(params, tile_global=8 if count(params, 2, 8) >= AUTO_GLOBAL else 9)
+        if _placeholder_bytes(shapes, small) > 0:
+            params = small
+    return params
+
+
 class GraphBatch:
     """Graph-replayed batched completion for batches up to a capacity.
 
@@ -82,25 +105,7 @@ class GraphBatch:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.capacity = [tuple(int(v) for v in s) for s in capacity]
         params = params or Params()
-        # as the library does for calls that see their frames: phase-1 tiles
-        # of 32 rows when 64-row ones would give the GPU fewer than two waves
-        # per SIMD, of 16 rows when 32-row ones would give fewer than one, of
-        # 8 rows when 16-row ones would give fewer than half; phase-2 tiles
-        # (the default chain only) of the tallest of 32, 16 and 8 rows that
-        # gives at least four (the plan and the captured launch share them);
-        # only tiles the chain supports
-        def count(phase, tid):
-            p = dataclasses.replace(params, **{"tile_local" if phase == 1 else "tile_global": tid})
-            return _tile_counts(p.to_c(), self.capacity)[phase - 1]
-        if params.tile_local == 0 and count(1, 0) < AUTO_LOCAL32:
-            tid = 7 if count(1, 7) >= AUTO_LOCAL16 else 8 if count(1, 8) >= AUTO_LOCAL8 else 9
-            small = dataclasses.replace(params, tile_local=tid)
-            if _placeholder_bytes(self.capacity, small) > 0:
-                params = small
-        if params.tile_global == 0 and count(2, 0) < AUTO_GLOBAL:
-            small = dataclasses.replace(params, tile_global=8 if count(2, 8) >= AUTO_GLOBAL else 9)
-            if _placeholder_bytes(self.capacity, small) > 0:
-                params = small
+        params = auto_tiles(params, self.capacity)   # the plan and the captured launch share them
         self.params = params
         self.cp = self.params.to_c()
         self.max_frames = len(self.capacity)

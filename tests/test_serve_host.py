@@ -227,3 +227,28 @@ def test_shapes_workspace_bytes_matches_layout():
     assert batch.shapes_workspace_bytes([(400, 1300)]) >= one
     lt, gt, cols = batch._tile_counts(Params().to_c(), [(375, 1242), (64, 64)])
     assert cols == 1306 and lt > 0 and gt > 0
+
+
+@pytest.mark.parametrize("shapes", [[(352, 1216)], [(375, 1242)], [(512, 2048)], [(1024, 4096)],
+                                    [(375, 1242)] * 4, [(375, 1242)] * 8, [(375, 1242)] * 16,
+                                    [(1024, 4096)] * 2, [(375, 1242)] * 64])
+@pytest.mark.parametrize("chain", ["default", "median3", "cross"])
+def test_graph_batch_tile_rule_matches_the_library(shapes, chain):
+    """batch.auto_tiles picks the tiles the library picks for calls that see
+    the frames: the batch workspace for the automatic ids (which covers the
+    library's pick and the default tiles) equals the larger of the two
+    layouts for the explicit ids batch.auto_tiles returns."""
+    from paper_1802_00036_amd import api, batch
+    from paper_1802_00036_amd.api import Params
+    p = {"default": Params(), "median3": Params(median_size=3),
+         "cross": Params(dilate_shape=api.SE_CROSS)}[chain]
+    picked = batch.auto_tiles(p, shapes)
+    lib_bytes = batch.shapes_workspace_bytes(shapes, p)
+    explicit = batch.shapes_workspace_bytes(shapes, picked)
+    # the library's default ids: the streaming kernels where the chain has them
+    tl = 5 if batch._placeholder_bytes(shapes, dataclasses.replace(p, tile_local=5, tile_global=1)) else 1
+    tg = 6 if batch._placeholder_bytes(shapes, dataclasses.replace(p, tile_local=tl, tile_global=6)) else 1
+    default = batch.shapes_workspace_bytes(shapes, dataclasses.replace(p, tile_local=tl, tile_global=tg))
+    assert lib_bytes == max(explicit, default)
+    if chain == "median3":
+        assert picked.tile_global == 0                  # 16- and 8-row phase-2 tiles: 5x5 median chains only
