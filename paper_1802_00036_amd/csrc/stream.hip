@@ -105,7 +105,7 @@ __device__ __forceinline__ int xcd_tile_s(int b, int g) {
 // registers.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 // A register copy the compiler cannot fold away.  Taking a prefetched row
-// out of its ring slot this way lets the prefetch of row r + 8 load into the
+// out of its ring slot this way lets the prefetch of row r + 4 load into the
 // slot's own register; otherwise the loop carries register copies of loads
 // still in flight, and every pass of the unrolled loop waits for all of them.
 __device__ __forceinline__ int detach(int v) {
@@ -1045,8 +1045,8 @@ __device__ __forceinline__ unsigned wave_or(unsigned v) {
 // One wave per column of phase-1 tiles and group of eight tile rows (the
 // waves of the group's first tile row) reads the records of those tiles
 // and queues the 32-row bands that may hold such a cell: the launch tile id,
-// and the frame index with the band in bits 24..25.  Frames under 3 rows or columns are left to phase 2, which
-// recomputes them whole.
+// and the frame index with the band in bits 24..25.  Frames under 3 rows or
+// columns are left to phase 2, which recomputes them whole.
 __global__ __launch_bounds__(kLanes) void k_fill_scan(FrameSource src, KParams kp, int lth) {
   const int lane = threadIdx.x;
   const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
