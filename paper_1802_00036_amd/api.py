@@ -42,11 +42,23 @@ class Params:
     extend_rows: int = 0                 # stage-5 reach above a column's top; 0 = to row 0
 
     def to_c(self) -> L.CParams:
-        c = L.CParams()
-        L.lib().ipb_params_default(ctypes.byref(c))
-        for f in dataclasses.fields(self):
-            setattr(c, f.name, getattr(self, f.name))
-        return c
+        """A fresh ipb_params for these values (the caller may change it)."""
+        key = tuple(self.__dict__.values())
+        c = _C_PARAMS.get(key)
+        if c is None:
+            c = L.CParams()
+            L.lib().ipb_params_default(ctypes.byref(c))
+            for f in dataclasses.fields(self):
+                setattr(c, f.name, getattr(self, f.name))
+            if len(_C_PARAMS) >= 256:
+                _C_PARAMS.clear()
+            _C_PARAMS[key] = c
+        return L.CParams.from_buffer_copy(c)
+
+
+# converted parameter sets by field values (a per-call conversion costs a
+# few microseconds, a sizeable share of one small frame's host time)
+_C_PARAMS: dict = {}
 
 
 def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
