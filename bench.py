@@ -43,7 +43,8 @@ PHASES = ["k_reset", "k_local_stream", "k_fill_scan+k_fill_tiles", "k_global_str
 # stage-4 map read + output write (phase 2)
 BYTES_PER_PX = {"k_local_stream": 8, "k_global_stream": 8}
 CSRC = os.path.join(ROOT, "paper_1802_00036_amd", "csrc")
-KERNEL_SOURCES = ("common.hpp", "networks.hpp", "median_net.hpp", "kernels.hip", "stream.hip", "api.hip")
+KERNEL_SOURCES = ("common.hpp", "networks.hpp", "median_net.hpp", "offsets.hpp", "kernels.hip", "stream.hip",
+                  "api.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_batched.json")
 PARAMS_TEXT = "diamond5 close5 fill7 extend fill31 median5 gauss5(binomial)"
 WORKLOADS = {
@@ -446,7 +447,11 @@ def bench_batch(args, workload, cpu, serve_host=None):
         pf_ms = b.time_per_frame(args.per_frame_steps)
         extra["per_frame_path"] = {"frames_per_s": round(b.n / (pf_ms / 1e3), 1), "ms_per_batch": round(pf_ms, 4)}
     if serve_host is not None:
-        extra["serving"] = serving_runs(serve_host, rates=(2000,), seconds=args.serve_seconds, modes=("batched",))
+        # the serving mix at a rate where batches form (8000 frames/s) and at
+        # an overload point (16000), the batcher beside the plain per-frame
+        # FIFO on the same arrival traces
+        extra["serving"] = serving_runs(serve_host, rates=(8000, 16000), seconds=args.serve_seconds,
+                                        modes=("batched", "per_frame"), warmup_s=0.5)
     cfgd = {"workload": WORKLOADS[workload], "id": workload, "frames": b.n, "pixels": b.px, "params": PARAMS_TEXT}
     if cfg in (2, 4):
         cfgd.update(H=b.shapes[0][0], W=b.shapes[0][1])
@@ -543,7 +548,7 @@ def main() -> None:
     ap.add_argument("--streams", type=int, default=3,
                     help="batched workloads: streams the timed batches are spread over (buffer sets are bound "
                          "to streams; batches on different streams overlap)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated frames per size for serving")
     ap.add_argument("--no-serving", action="store_true", help="c2: skip the serving summary")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")

@@ -23,7 +23,8 @@
  *
  * Conventions shared by every entry point:
  *   - Maps are float32, row-major, pitch = W, in DEVICE memory.  1 <= H, W and
- *     H * W <= 2^30 (the kernels address a map with 32-bit byte offsets).
+ *     H * W < 2^30 (the kernels address a map, and a scratch slot just past
+ *     it, with 32-bit byte offsets).
  *   - Ownership: the caller owns every buffer (inputs, outputs, workspace) and
  *     keeps it alive until the stream work completes.  The library keeps no
  *     pointer after a call returns.
@@ -33,7 +34,10 @@
  *     surface at the caller's next stream synchronisation, as with any HIP
  *     launch.  The library never synchronises the stream.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *   - Results are bitwise deterministic: the only atomic is an integer min.
+ *   - Results are bitwise deterministic.  The kernels' atomics are integer
+ *     mins (column tops) and adds that hand out queue positions; every queued
+ *     item writes cells no other item writes, so no result depends on the
+ *     order of a queue.
  */
 #ifndef IPB_H
 #define IPB_H
@@ -156,11 +160,13 @@ typedef struct {
 size_t ipb_batch_workspace_bytes(const ipb_frame* frames, int n, const ipb_params* p);
 
 /* Complete n frames (host array of descriptors with device pointers).  The
- * launch plan is built in a pinned staging buffer of the library and copied
- * into the workspace on the stream (the staging buffer is reused only after
- * that copy completed); the caller's array may be reused when the call
- * returns.  Not capturable into a graph: use ipb_batch_plan and
- * ipb_complete_planned for that. */
+ * launch plan is built in host memory of the calling thread and written into
+ * the workspace by small upload kernels on the stream that take it in their
+ * arguments, so the caller's array may be reused when the call returns.
+ * Allocates no device or pinned memory, synchronises nothing, reads no
+ * device memory on the host: the call can be captured into a graph (whose
+ * replays then complete the same frames; for new frames per replay use
+ * ipb_batch_plan and ipb_complete_planned). */
 int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p,
                        void* ws, size_t ws_bytes, void* stream);
 

@@ -66,6 +66,23 @@ def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _launch_stream(stream: Optional[torch.cuda.Stream], device: torch.device):
+    """The stream the call runs on and whether it is another than the
+    current one (then buffers the call takes from torch's allocator are
+    allocated under it, and tensors from the current stream are recorded on
+    it, so that torch's caching allocator does not hand their memory to other
+    work while the kernels still use it)."""
+    cur = torch.cuda.current_stream(device)
+    if stream is None or stream == cur:
+        return cur, False
+    return stream, True
+
+
+def _record(stream: torch.cuda.Stream, *tensors: torch.Tensor) -> None:
+    for t in tensors:
+        t.record_stream(stream)
+
+
 def _check_map(t: torch.Tensor, name: str) -> None:
     if not isinstance(t, torch.Tensor) or t.dim() != 2:
         raise ValueError(f"{name} must be a 2-D tensor")
@@ -94,20 +111,36 @@ def complete(depth: torch.Tensor, params: Optional[Params] = None, out: Optional
 def complete_stage(depth: torch.Tensor, last_stage: int, params: Optional[Params] = None,
                    out: Optional[torch.Tensor] = None,
                    stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
-    """Map after stage `last_stage` (1..9; stages 1-8 in the inverted domain)."""
+    """Map after stage `last_stage` (1..9; stages 1-8 in the inverted domain).
+
+    Runs on `stream` (default: the current stream); the caller orders that
+    stream after whatever produced `depth`.  With another stream than the
+    current one, the workspace and a default `out` are allocated under
+    `stream`, and `depth` and a given `out` are recorded on it."""
     _check_map(depth, "depth")
     H, W = depth.shape
-    if out is None:
-        out = torch.empty_like(depth)
-    _check_map(out, "out")
+    s, other = _launch_stream(stream, depth.device)
     p = (params or Params()).to_c()
     nb = int(L.lib().ipb_workspace_bytes(H, W, ctypes.byref(p)))
     if nb == 0:
         L.check(L.IPB_ERR_INVALID_ARG, "ipb_workspace_bytes")
-    ws = _workspace(nb, depth.device)
+    if other:
+        if out is not None:
+            _check_map(out, "out")
+            _record(s, out)
+        _record(s, depth)
+        with torch.cuda.stream(s):
+            if out is None:
+                out = torch.empty_like(depth)
+            ws = _workspace(nb, depth.device)
+    else:
+        if out is None:
+            out = torch.empty_like(depth)
+        ws = _workspace(nb, depth.device)
+    _check_map(out, "out")
     st = L.lib().ipb_complete_stage(ctypes.c_void_p(depth.data_ptr()), H, W, ctypes.byref(p),
                                     ctypes.c_void_p(out.data_ptr()), last_stage,
-                                    ctypes.c_void_p(ws.data_ptr()), nb, _stream_handle(stream))
+                                    ctypes.c_void_p(ws.data_ptr()), nb, ctypes.c_void_p(s.cuda_stream))
     L.check(st, "ipb_complete_stage")
     return out
 
@@ -118,12 +151,21 @@ def complete_alloc(depth: torch.Tensor, params: Optional[Params] = None, out: Op
     (ipb_complete)."""
     _check_map(depth, "depth")
     H, W = depth.shape
-    if out is None:
+    s, other = _launch_stream(stream, depth.device)
+    if other:
+        if out is not None:
+            _check_map(out, "out")
+            _record(s, out)
+        _record(s, depth)
+        with torch.cuda.stream(s):
+            if out is None:
+                out = torch.empty_like(depth)
+    elif out is None:
         out = torch.empty_like(depth)
     _check_map(out, "out")
     p = (params or Params()).to_c()
     st = L.lib().ipb_complete(ctypes.c_void_p(depth.data_ptr()), H, W, ctypes.byref(p),
-                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s.cuda_stream))
     L.check(st, "ipb_complete")
     return out
 
@@ -152,18 +194,26 @@ def batch_workspace_bytes(frames: Sequence[torch.Tensor], params: Optional[Param
 def complete_batch(frames: Sequence[torch.Tensor], params: Optional[Params] = None,
                    outs: Optional[Sequence[torch.Tensor]] = None,
                    stream: Optional[torch.cuda.Stream] = None) -> List[torch.Tensor]:
-    """Complete frames of any sizes together (ipb_complete_batch)."""
+    """Complete frames of any sizes together (ipb_complete_batch).  Stream
+    rules as complete_stage()."""
     frames = list(frames)
     if not frames:
         return []
-    outs = list(outs) if outs is not None else [torch.empty_like(f) for f in frames]
-    arr = frames_array(frames, outs)
-    p = (params or Params()).to_c()
-    nb = int(L.lib().ipb_batch_workspace_bytes(arr, len(frames), ctypes.byref(p)))
-    if nb == 0:
-        L.check(L.IPB_ERR_INVALID_ARG, "ipb_batch_workspace_bytes")
-    ws = _workspace(nb, frames[0].device)
+    dev = frames[0].device
+    s, other = _launch_stream(stream, dev)
+    if other:
+        _record(s, *frames)
+        if outs is not None:
+            _record(s, *outs)
+    with torch.cuda.stream(s):
+        outs = list(outs) if outs is not None else [torch.empty_like(f) for f in frames]
+        arr = frames_array(frames, outs)
+        p = (params or Params()).to_c()
+        nb = int(L.lib().ipb_batch_workspace_bytes(arr, len(frames), ctypes.byref(p)))
+        if nb == 0:
+            L.check(L.IPB_ERR_INVALID_ARG, "ipb_batch_workspace_bytes")
+        ws = _workspace(nb, dev)
     st = L.lib().ipb_complete_batch(arr, len(frames), ctypes.byref(p), ctypes.c_void_p(ws.data_ptr()), nb,
-                                    _stream_handle(stream))
+                                    ctypes.c_void_p(s.cuda_stream))
     L.check(st, "ipb_complete_batch")
     return outs

@@ -202,6 +202,32 @@ class _Timer:
         return a.elapsed_time(b) * 1e3 / (reps * streams)
 
 
+def tune_key(frames: Sequence[torch.Tensor], params: Params, streams: int = 1) -> str:
+    """Cache key of a batch: device, parameters, batch signature (and the
+    stream count when batches run in flight)."""
+    shapes = [tuple(f.shape) for f in frames]
+    key = "|".join((device_signature(frames[0].device), params_signature(params), batch_signature(shapes)))
+    return key + (f"|streams{streams}" if streams > 1 else "")
+
+
+def lookup(frames: Sequence[torch.Tensor], params: Optional[Params] = None, streams: int = 1,
+           user_cache: bool = True, shipped: bool = True) -> Optional[Params]:
+    """The cached tiles for batches like `frames` without timing anything:
+    the user cache's entry, else (shipped) the package table's; None if
+    neither has one."""
+    p0 = params or Params()
+    frames = list(frames)
+    if not frames:
+        return None
+    key = tune_key(frames, p0, streams)
+    hit = _load_cache(cache_path()).get(key) if user_cache else None
+    if hit is None and shipped:
+        hit = _load_cache(SHIPPED_TABLE).get(key)
+    if not hit:
+        return None
+    return dataclasses.replace(p0, tile_local=int(hit["tile_local"]), tile_global=int(hit["tile_global"]))
+
+
 def candidate_ids(phase: int) -> List[int]:
     return list(range(1, int(L.lib().ipb_tile_count(phase)) + 1))
 
@@ -218,15 +244,12 @@ def tune(frames: Sequence[torch.Tensor], params: Optional[Params] = None, reps: 
     frames = list(frames)
     if not frames:
         return p0
-    shapes = [tuple(f.shape) for f in frames]
-    key = "|".join((device_signature(frames[0].device), params_signature(p0), batch_signature(shapes)))
-    if streams > 1:
-        key += f"|streams{streams}"
+    key = tune_key(frames, p0, streams)
     path = cache_path()
     if use_cache:
-        hit = _load_cache(path).get(key) or (_load_cache(SHIPPED_TABLE).get(key) if use_shipped else None)
-        if hit:
-            return dataclasses.replace(p0, tile_local=int(hit["tile_local"]), tile_global=int(hit["tile_global"]))
+        hit = lookup(frames, p0, streams, user_cache=True, shipped=use_shipped)
+        if hit is not None:
+            return hit
     stream = torch.cuda.Stream(device=frames[0].device)
     with torch.cuda.stream(stream):
         outs = [torch.empty_like(f) for f in frames]

@@ -10,6 +10,7 @@
 
 #include "common.hpp"
 #include "ipb.h"
+#include "offsets.hpp"
 
 using namespace ipb;
 
@@ -25,11 +26,10 @@ int hip_fail(hipError_t e) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// every byte offset within a map fits in 32 bits (the kernels address maps
-// with 32-bit offsets from the map's base)
-bool size_ok(int H, int W) {
-  return H >= 1 && W >= 1 && static_cast<long long>(H) * W <= (1LL << 30);
-}
+// every byte offset within a map, and the scratch slot just past it, fits
+// in 32 bits (the kernels address maps with 32-bit offsets from the map's
+// base): H * W < 2^30
+bool size_ok(int H, int W) { return cells_ok(H, W); }
 
 // Parameters resolved into what the kernels take.
 struct Resolved {
@@ -236,20 +236,9 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-// Pinned staging slots for plans copied by ipb_complete_batch; a slot is
-// reused only after the copy that last read it has completed.
-struct StagingSlot {
-  void* host = nullptr;
-  size_t cap = 0;
-  hipEvent_t ev = nullptr;
-  bool pending = false;
-};
-struct Staging {
-  std::mutex mu;
-  StagingSlot slot[4];
-  int next = 0;
-};
-Staging g_staging[64];
+// Host memory in which ipb_complete_batch builds a plan before its upload
+// kernels take it by value; grown as needed, reused by the calling thread.
+thread_local std::vector<int32_t> t_plan;
 
 // Fill a plan (host memory) for frames whose workspace is ws.
 void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, void* plan_host) {
@@ -623,42 +612,18 @@ int ipb_complete_batch(const ipb_frame* frames, int n, const ipb_params* p, void
     if (overlaps(ws, ws_bytes, frames[i].in, nb) || overlaps(ws, ws_bytes, frames[i].out, nb))
       return IPB_ERR_INVALID_ARG;
   }
-  int dev = 0;
-  st = device_cus(&dev);
-  if (st != IPB_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // the plan is built in host memory of this thread and reaches the
+  // workspace in the arguments of upload kernels on the stream: no staging
+  // buffer, no copy to wait for, so the call can be captured into a graph
   const size_t pb = ipb_batch_plan_bytes(n);
-
-  Staging& stg = g_staging[dev];
-  std::lock_guard<std::mutex> g(stg.mu);
-  StagingSlot& slot = stg.slot[stg.next];
-  stg.next = (stg.next + 1) % 4;
-  hipError_t e;
-  if (slot.pending) {
-    e = hipEventSynchronize(slot.ev);   // the copy that last read this slot
-    if (e != hipSuccess) return hip_fail(e);
-    slot.pending = false;
-  }
-  if (slot.ev == nullptr) {
-    e = hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  if (slot.cap < pb) {
-    if (slot.host) (void)hipHostFree(slot.host);
-    slot.host = nullptr;
-    slot.cap = 0;
-    e = hipHostMalloc(&slot.host, pb, hipHostMallocDefault);
-    if (e != hipSuccess) return hip_fail(e);
-    slot.cap = pb;
-  }
-  build_plan(frames, n, r, ws, slot.host);
-  const auto* hdr = static_cast<const PlanHeader*>(slot.host);
+  if (t_plan.size() < pb / sizeof(int32_t)) t_plan.resize(pb / sizeof(int32_t));
+  void* host = t_plan.data();
+  build_plan(frames, n, r, ws, host);
+  const auto* hdr = static_cast<const PlanHeader*>(host);
   const int lt = hdr->ltiles, gt = hdr->gtiles, cols = hdr->ncols;
-  e = hipMemcpyAsync(ws, slot.host, pb, hipMemcpyHostToDevice, s);
+  hipError_t e = launch_plan_upload(host, pb, ws, s);
   if (e != hipSuccess) return hip_fail(e);
-  e = hipEventRecord(slot.ev, s);
-  if (e != hipSuccess) return hip_fail(e);
-  slot.pending = true;
   bool tiny = false;
   for (int i = 0; i < n; ++i) tiny = tiny || frames[i].H < 3 || frames[i].W < 3;
   return planned(ws, r, -1, lt, gt, cols, tiny, stream);

@@ -141,6 +141,10 @@ constexpr int kFillTag = (int)0x80000000u;
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_reset(const FrameSource& src, int max_items, hipStream_t s);
+// Copies a host plan (bytes, a multiple of 4) to device memory through the
+// arguments of small kernels on the stream, kPlanChunkWords ints per launch.
+constexpr int kPlanChunkWords = 896;   // 3584 bytes of kernel arguments
+hipError_t launch_plan_upload(const void* plan_host, size_t bytes, void* plan_dev, hipStream_t s);
 hipError_t launch_global_slow(const FrameSource& src, const KParams& kp, int stream_rows, int stream_cols,
                               int grid, hipStream_t s);
 int slow_subtiles(int stream_rows, int stream_cols);

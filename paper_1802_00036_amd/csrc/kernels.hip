@@ -11,6 +11,9 @@
 // and rounds once to fp32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+
 #include "common.hpp"
 #include "median_net.hpp"
 
@@ -648,6 +651,16 @@ __global__ __launch_bounds__(kThreads) void k_reset(FrameSource src) {
   }
 }
 
+// A launch plan built on the host travels to the workspace in kernel
+// arguments, a chunk per launch: the call then needs no host staging
+// buffer, no copy engine and no wait, and can be captured into a graph.
+struct PlanChunk {
+  int32_t words[kPlanChunkWords];
+};
+__global__ __launch_bounds__(kThreads) void k_plan_upload(PlanChunk c, int32_t* dst, int nwords) {
+  for (int i = threadIdx.x; i < nwords; i += kThreads) dst[i] = c.words[i];
+}
+
 // ---------------------------------------------------------------------------
 // Tile shapes.
 struct Shape { int rows, cols; };
@@ -682,6 +695,21 @@ hipError_t launch_reset(const FrameSource& src, int max_items, hipStream_t s) {
   if (grid > 1024) grid = 1024;
   hipLaunchKernelGGL(k_reset, dim3(grid), dim3(kThreads), 0, s, src);
   return hipGetLastError();
+}
+
+hipError_t launch_plan_upload(const void* plan_host, size_t bytes, void* plan_dev, hipStream_t s) {
+  const int32_t* src = static_cast<const int32_t*>(plan_host);
+  int32_t* dst = static_cast<int32_t*>(plan_dev);
+  const size_t words = (bytes + 3) / 4;
+  for (size_t w0 = 0; w0 < words; w0 += kPlanChunkWords) {
+    const int nw = (int)std::min<size_t>(kPlanChunkWords, words - w0);
+    PlanChunk c;
+    std::memcpy(c.words, src + w0, sizeof(int32_t) * nw);
+    hipLaunchKernelGGL(k_plan_upload, dim3(1), dim3(kThreads), 0, s, c, dst + w0, nw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_local(const FrameSource& src, const KParams& kp, int tile_id, int halo, int grid,

@@ -34,6 +34,7 @@
 
 #include "common.hpp"
 #include "networks.hpp"
+#include "offsets.hpp"
 
 #pragma clang fp contract(off)
 
@@ -226,7 +227,7 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   gchar* rec = (gchar*)(char*)f.v6p + 4 * (size_t)(ty0 / TH) * W;   // uniform row base; lanes add ua / ub
   gcfloat* in = gcf(f.in);
   const unsigned W4 = 4u * (unsigned)W;
-  const unsigned sink = (unsigned)H * W4;                 // scratch slot past the stage-4 map
+  const unsigned sink = sink_offset(H, W);               // scratch slot past the stage-4 map
   const unsigned uH = (unsigned)H;
 
   // input rows are fetched 4 rows ahead of their use (a wave's row step

@@ -18,7 +18,24 @@ server
   another slot while earlier batches still run, so their work overlaps on the
   device (continuous batching, not a queue in front of one batch);
 * polls the end-of-batch events; a request's latency is the time its event
-  was observed complete minus its scheduled arrival.
+  was observed complete minus its scheduled arrival;
+* handles failures: a launch (or an event query) that raises marks its
+  batch failed, and each of its requests is retried once alone; a request
+  that fails alone is marked failed with the error, and its memory leaves
+  the budget.  Requests can be cancelled, and requests still waiting for a
+  launch when their timeout passes are dropped with status "timeout".
+
+Memory admission counts, besides the outputs of admitted requests, what the
+executor keeps resident (workspaces of its engines, released output buffers
+kept for reuse); when nothing runs and the next request does not fit, the
+executor is asked to drop idle resident memory first.
+
+Stream order: a request's frame may come from work on another stream.  The
+GPU executors record an event on the submitting thread's current stream when
+the request is submitted (or take the client's own event), and the slot
+stream waits for it before the launch reads the frame; an output buffer
+that returns to the pool is reused only after an event recorded on the
+releasing thread's current stream.
 
 Every frame is completed independently of the others in its batch (Sec. II),
 so a result does not depend on what it was batched with.
@@ -61,11 +78,18 @@ class Request:
     params: object = None
     bucket: Hashable = None
     nbytes: int = 0
-    status: str = "queued"             # queued, admitted, running, done, rejected
+    # queued, admitted, running, done, released, rejected, failed, cancelled, timeout
+    status: str = "queued"
     out: object = None
     t_admit: float = math.nan
     t_launch: float = math.nan
     t_done: float = math.nan
+    deadline: float = math.inf         # launch by then, or the request times out
+    ready: object = None               # event after the work that produced `frame` (GPU executors)
+    attempts: int = 0                  # launches that failed
+    solo: bool = False                 # to be launched alone (a retry after a failed batch)
+    cancelled: bool = False            # cancelled while running: released when it completes
+    error: Optional[str] = None
 
     @property
     def latency(self) -> float:
@@ -79,6 +103,10 @@ class Executor:
     slots: int = 1
     in_order: bool = False
 
+    def submitted(self, req: Request) -> None:
+        """A request entered the server (GPU executors note the stream order
+        of its frame here)."""
+
     def launch(self, slot: int, bucket: Hashable, reqs: Sequence[Request]) -> object:
         raise NotImplementedError
 
@@ -91,13 +119,24 @@ class Executor:
     def recycle(self, outs: Sequence[object]) -> None:
         """Output buffers the client has finished with."""
 
+    def resident_bytes(self) -> int:
+        """Device memory the executor keeps between batches."""
+        return 0
+
+    def trim(self, target: int) -> None:
+        """Drop idle resident memory until at most `target` bytes remain (if
+        it can); called only while no batch runs."""
+
 
 class Server:
     def __init__(self, executor: Executor, mem_budget: int, max_batch: int = 16, max_queue: int = 100000,
                  bucket_fn: Callable[[Tuple[int, int]], Hashable] = default_bucket,
-                 clock: Callable[[], float] = time.perf_counter, keep_outputs: bool = True):
+                 clock: Callable[[], float] = time.perf_counter, keep_outputs: bool = True,
+                 timeout: Optional[float] = None):
         if mem_budget <= 0 or max_batch < 1:
             raise ValueError("mem_budget and max_batch must be positive")
+        if timeout is not None and not timeout > 0:
+            raise ValueError("timeout must be positive")
         self.ex = executor
         self.mem_budget = int(mem_budget)
         self.max_batch = int(max_batch)
@@ -105,61 +144,173 @@ class Server:
         self.bucket_fn = bucket_fn
         self.clock = clock
         self.keep_outputs = keep_outputs
+        self.timeout = timeout
         self.t0 = clock()
         self.waiting: Deque[Request] = collections.deque()          # not yet admitted, arrival order
         self.admitted: Dict[Hashable, Deque[Request]] = collections.OrderedDict()
+        self.retry: Deque[Request] = collections.deque()            # admitted, to be launched alone
         self.in_use = 0                                             # admitted, unreleased output bytes
         self.running: "collections.OrderedDict[int, Tuple[object, List[Request]]]" = collections.OrderedDict()
         self.free_slots: List[int] = list(range(executor.slots - 1, -1, -1))
         self.done: List[Request] = []
         self.rejected: List[Request] = []
+        self.failed: List[Request] = []
+        self.cancelled: List[Request] = []
+        self.timed_out: List[Request] = []
         self.batches = 0
+        self.failed_batches = 0
         self.launch_s = 0.0                                         # host seconds spent in launches
         self.peak_in_use = 0
         self._next_id = 0
+        self._deadlines = False                                     # some request has a finite deadline
 
     def now(self) -> float:
         return self.clock() - self.t0
 
     # ---------------------------------------------------------------- intake --
     def submit(self, frame, arrival: Optional[float] = None, params=None,
-               shape: Optional[Tuple[int, int]] = None) -> Request:
+               shape: Optional[Tuple[int, int]] = None, ready=None, timeout: Optional[float] = None) -> Request:
+        """Queue one frame.  ready: an event marking the end of the work that
+        produced the frame (GPU executors otherwise record one on the current
+        stream); timeout: seconds from arrival by which the request must be
+        launched (default: the server's)."""
         shape = tuple(shape if shape is not None else frame.shape)
         req = Request(self._next_id, frame, shape, self.now() if arrival is None else arrival, params)
         self._next_id += 1
         req.bucket = (self.bucket_fn(shape), _params_key(params))
         req.nbytes = 4 * shape[0] * shape[1]
+        t_out = timeout if timeout is not None else self.timeout
+        if t_out is not None:
+            req.deadline = req.arrival + t_out
+            self._deadlines = True
         if req.nbytes > self.mem_budget or len(self.waiting) >= self.max_queue:
             req.status = "rejected"
             self.rejected.append(req)
             return req
+        req.ready = ready
+        self.ex.submitted(req)
         self.waiting.append(req)
         return req
 
+    def cancel(self, req: Request) -> bool:
+        """Cancel a request.  One that waits or is admitted leaves at once
+        (status "cancelled", its memory leaves the budget); one that runs
+        cannot be stopped on the device: it is marked, and when its batch
+        completes its output is released and its status is "cancelled".
+        Returns False if the request had already finished."""
+        if req.status == "queued":
+            self.waiting.remove(req)
+        elif req.status == "admitted":
+            if req.solo:
+                self.retry.remove(req)
+            else:
+                self.admitted[req.bucket].remove(req)
+            self.in_use -= req.nbytes
+        elif req.status == "running":
+            req.cancelled = True
+            return True
+        else:
+            return False
+        req.status = "cancelled"
+        self.cancelled.append(req)
+        return True
+
     # ------------------------------------------------------------ scheduling --
+    def _finish(self, reqs: Sequence[Request], outs: Sequence[object], t: float) -> List[Request]:
+        done, back = [], []
+        for r, o in zip(reqs, outs):
+            r.t_done = t
+            r.out = o
+            r.status = "done"
+            if r.cancelled:
+                back.append(r)
+                self.cancelled.append(r)
+                continue
+            done.append(r)
+            if not self.keep_outputs:
+                back.append(r)
+        self.release_many(back)
+        for r in back:
+            if r.cancelled:
+                r.status = "cancelled"
+        self.done.extend(done)
+        return done
+
+    def _fail(self, reqs: Sequence[Request], exc: BaseException) -> None:
+        """A batch failed (its launch or its completion raised): requests
+        that failed in a batch are retried once alone; one that failed alone
+        is marked failed (cancelled ones just leave)."""
+        self.failed_batches += 1
+        for r in reqs:
+            r.attempts += 1
+            if r.cancelled:
+                r.status = "cancelled"
+                self.in_use -= r.nbytes
+                self.cancelled.append(r)
+            elif r.solo or r.attempts >= 2:
+                r.status = "failed"
+                r.error = f"{type(exc).__name__}: {exc}"
+                self.in_use -= r.nbytes
+                self.failed.append(r)
+            else:
+                r.status = "admitted"
+                r.solo = True
+                self.retry.append(r)
+
     def _poll(self) -> List[Request]:
         finished = []
         for s, (handle, reqs) in list(self.running.items()):
-            if not self.ex.ready(handle):
+            try:
+                ok = self.ex.ready(handle)
+                outs = self.ex.outputs(handle) if ok else None
+            except Exception as exc:          # the batch's device work failed
+                del self.running[s]
+                self.free_slots.append(s)
+                self._fail(reqs, exc)
+                continue
+            if not ok:
                 if self.ex.in_order:
                     break
                 continue
-            t = self.now()
-            outs = self.ex.outputs(handle)
-            for r, o in zip(reqs, outs):
-                r.t_done = t
-                r.status = "done"
-                r.out = o
-                if not self.keep_outputs:
-                    self.release(r)
             del self.running[s]
             self.free_slots.append(s)
-            self.done.extend(reqs)
-            finished.extend(reqs)
+            finished.extend(self._finish(reqs, outs, self.now()))
         return finished
 
+    def _expire(self) -> None:
+        """Requests not launched by their deadline time out."""
+        if not self._deadlines:
+            return
+        t = self.now()
+        keep = collections.deque()
+        for r in self.waiting:
+            if r.deadline < t:
+                r.status = "timeout"
+                self.timed_out.append(r)
+            else:
+                keep.append(r)
+        self.waiting = keep
+        for q in list(self.admitted.values()) + [self.retry]:
+            late = [r for r in q if r.deadline < t]
+            for r in late:
+                q.remove(r)
+                r.status = "timeout"
+                self.in_use -= r.nbytes
+                self.timed_out.append(r)
+
+    def _reserved(self) -> int:
+        return self.in_use + self.ex.resident_bytes()
+
     def _admit(self) -> None:
-        while self.waiting and self.in_use + self.waiting[0].nbytes <= self.mem_budget:
+        while self.waiting:
+            need = self.waiting[0].nbytes
+            if self._reserved() + need > self.mem_budget:
+                if self.running or any(self.admitted.values()) or self.retry:
+                    break
+                # nothing runs: let the executor drop idle resident memory
+                self.ex.trim(max(0, self.mem_budget - self.in_use - need))
+                if self._reserved() + need > self.mem_budget:
+                    break
             r = self.waiting.popleft()
             r.status = "admitted"
             r.t_admit = self.now()
@@ -169,37 +320,50 @@ class Server:
 
     def _launch(self) -> None:
         while self.free_slots:
-            live = [(q[0].rid, b) for b, q in self.admitted.items() if q]
-            if not live:
-                return
+            if self.retry:
+                reqs = [self.retry.popleft()]           # a retry runs alone
+                bucket = reqs[0].bucket
+            else:
+                live = [(q[0].rid, b) for b, q in self.admitted.items() if q]
+                if not live:
+                    return
+                _, bucket = min(live, key=lambda v: v[0])      # the bucket of the oldest admitted request
+                q = self.admitted[bucket]
+                reqs = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
             s = self.free_slots.pop()
-            _, bucket = min(live, key=lambda v: v[0])      # the bucket of the oldest admitted request
-            q = self.admitted[bucket]
-            reqs = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
             t = self.now()
             for r in reqs:
                 r.status = "running"
                 r.t_launch = t
-            handle = self.ex.launch(s, bucket, reqs)
-            self.launch_s += self.now() - t
+            try:
+                handle = self.ex.launch(s, bucket, reqs)
+            except Exception as exc:                   # nothing of the batch was queued, or its queue failed
+                self.free_slots.append(s)
+                self._fail(reqs, exc)
+                continue
+            finally:
+                self.launch_s += self.now() - t
             self.running[s] = (handle, reqs)
             self.batches += 1
 
     def step(self) -> List[Request]:
-        """One scheduling round: collect finished batches, admit, launch."""
+        """One scheduling round: collect finished batches, drop requests past
+        their deadline, admit, launch."""
         finished = self._poll()
+        self._expire()
         self._admit()
         self._launch()
         return finished
 
     def idle(self) -> bool:
-        return not self.waiting and not any(self.admitted.values()) and not self.running
+        return not self.waiting and not any(self.admitted.values()) and not self.running and not self.retry
 
     def stalled(self) -> bool:
         """Requests wait, nothing runs or is admitted, and the next one does
-        not fit: only releasing outputs can make progress."""
-        return (bool(self.waiting) and not self.running and not any(self.admitted.values())
-                and self.in_use + self.waiting[0].nbytes > self.mem_budget)
+        not fit even after the executor dropped its idle memory: only
+        releasing outputs can make progress."""
+        return (bool(self.waiting) and not self.running and not any(self.admitted.values()) and not self.retry
+                and self._reserved() + self.waiting[0].nbytes > self.mem_budget)
 
     def drain(self, timeout: float = 60.0) -> None:
         t_end = self.now() + timeout
@@ -212,13 +376,21 @@ class Server:
 
     def release(self, req: Request) -> None:
         """Hand a finished request's output buffer back (its bytes leave the
-        budget; the buffer is reused)."""
-        if req.status != "done" or req.out is None:
-            return
-        self.ex.recycle([req.out])
-        req.out = None
-        req.status = "released"
-        self.in_use -= req.nbytes
+        budget; the buffer is reused once the work queued so far on the
+        current stream, such as the client's reads of it, is done)."""
+        self.release_many([req])
+
+    def release_many(self, reqs: Sequence[Request]) -> None:
+        outs = []
+        for req in reqs:
+            if req.status != "done" or req.out is None:
+                continue
+            outs.append(req.out)
+            req.out = None
+            req.status = "released"
+            self.in_use -= req.nbytes
+        if outs:
+            self.ex.recycle(outs)
 
     # ------------------------------------------------------------- statistics --
     def stats(self, since: float = 0.0) -> dict:
@@ -227,8 +399,9 @@ class Server:
         requests that arrived at or after `since`."""
         span = [r for r in self.done if r.arrival >= since]
         lat = np.array([r.latency for r in span], np.float64)
-        out = {"completed": int(lat.size), "rejected": len(self.rejected), "batches": self.batches,
-               "peak_mem_bytes": int(self.peak_in_use)}
+        out = {"completed": int(lat.size), "rejected": len(self.rejected), "failed": len(self.failed),
+               "cancelled": len(self.cancelled), "timed_out": len(self.timed_out), "batches": self.batches,
+               "failed_batches": self.failed_batches, "peak_mem_bytes": int(self.peak_in_use)}
         if lat.size:
             wait = np.array([r.t_launch - r.arrival for r in span], np.float64)
             svc = np.array([r.t_done - r.t_launch for r in span], np.float64)
@@ -283,24 +456,62 @@ def run_trace(server: Server, frames: Sequence, arrivals: Sequence[float], param
 class BufferPool:
     """Resident output buffers by shape: a released buffer is reused by the
     next request of that shape, so steady-state serving allocates nothing.
-    A buffer is handed back only after the batch that wrote it completed and
-    the client released it, so reuse on any stream is ordered."""
+    A buffer comes back only after the batch that wrote it completed and the
+    client released it; the release records an event on the releasing
+    thread's current stream (where the client read the buffer), and the next
+    writer's stream waits for it.  New buffers are allocated under the stream
+    that first writes them."""
 
     def __init__(self, device):
         self.device = device
-        self.free: Dict[Tuple[int, int], List[object]] = collections.defaultdict(list)
+        self.free: Dict[Tuple[int, int], List[Tuple[object, object]]] = collections.defaultdict(list)
         self.allocated = 0
+        self.free_bytes = 0
 
-    def get(self, shape: Tuple[int, int]):
+    def get(self, shape: Tuple[int, int], stream):
+        """A buffer of `shape` that `stream` may write (the stream is made to
+        wait for the buffer's last reader)."""
         lst = self.free.get(shape)
         if lst:
-            return lst.pop()
+            buf, ev = lst.pop()
+            self.free_bytes -= 4 * shape[0] * shape[1]
+            if ev is not None:
+                stream.wait_event(ev)
+            return buf
         self.allocated += 1
-        return torch.empty(shape, dtype=torch.float32, device=self.device)
+        with torch.cuda.stream(stream):
+            return torch.empty(shape, dtype=torch.float32, device=self.device)
 
     def put(self, bufs: Sequence[object]) -> None:
+        if not bufs:
+            return
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(self.device))
         for b in bufs:
-            self.free[tuple(b.shape)].append(b)
+            self.free[tuple(b.shape)].append((b, ev))
+            self.free_bytes += 4 * b.numel()
+
+    def clear(self) -> None:
+        self.free.clear()
+        self.free_bytes = 0
+
+
+def _wait_inputs(stream, reqs: Sequence[Request]) -> None:
+    """Order `stream` after the work that produced the requests' frames."""
+    seen = set()
+    for r in reqs:
+        if r.ready is not None and id(r.ready) not in seen:
+            seen.add(id(r.ready))
+            stream.wait_event(r.ready)
+
+
+def _note_submit(req: Request, device) -> None:
+    """Record, when the client gave no event, one on the current stream: the
+    frame is ready once the work queued there so far is done."""
+    if req.ready is None:
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(device))
+        req.ready = ev
 
 
 class GraphExecutor(Executor):
@@ -329,7 +540,8 @@ class GraphExecutor(Executor):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.default_params = default_params or Params()
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
-        self.engines: Dict[Tuple[int, Hashable, int], object] = {}
+        # engines by (slot, bucket, tier), least recently used first
+        self.engines: "collections.OrderedDict[Tuple[int, Hashable, int], object]" = collections.OrderedDict()
         self.pool = BufferPool(self.device)
 
     def _engine(self, slot: int, bucket: Hashable, params, n: int):
@@ -342,7 +554,29 @@ class GraphExecutor(Executor):
             eng = GraphBatch([(Hb, Wb)] * tier, params or self.default_params, device=self.device,
                              stream=self.streams[slot])
             self.engines[key] = eng
+        else:
+            self.engines.move_to_end(key)
         return eng
+
+    def submitted(self, req: Request) -> None:
+        _note_submit(req, self.device)
+
+    def resident_bytes(self) -> int:
+        """Engine workspaces and plans, the per-slot workspaces of lone
+        requests and the released output buffers kept for reuse."""
+        eng = sum(e.ws_bytes + e.plan_bytes for e in self.engines.values())
+        return eng + sum(self.ws_bytes.values()) + self.pool.free_bytes
+
+    def trim(self, target: int) -> None:
+        """Drop pooled outputs, then least recently used engines and the
+        per-slot workspaces, until at most `target` bytes stay resident (only
+        called while nothing runs, so nothing dropped is in use)."""
+        self.pool.clear()
+        while self.engines and self.resident_bytes() > target:
+            self.engines.popitem(last=False)
+        if self.resident_bytes() > target:
+            self.ws.clear()
+            self.ws_bytes.clear()
 
     def warm(self, bucket_params: Sequence[Tuple[Hashable, object]]) -> None:
         """Capture the graphs of these buckets on every slot and tier ahead
@@ -373,7 +607,8 @@ class GraphExecutor(Executor):
             with torch.cuda.stream(stream):
                 self.ws[slot] = _workspace(need, self.device)
             self.ws_bytes[slot] = need
-        o = self.pool.get(r.shape)
+        o = self.pool.get(r.shape, stream)
+        _wait_inputs(stream, [r])
         L.check(lib.ipb_complete_ws(ctypes.c_void_p(r.frame.data_ptr()), H, W, ctypes.byref(cp),
                                     ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(self.ws[slot].data_ptr()),
                                     self.ws_bytes[slot], ctypes.c_void_p(stream.cuda_stream)), "ipb_complete_ws")
@@ -385,7 +620,8 @@ class GraphExecutor(Executor):
         if self.direct_single and len(reqs) == 1:
             return self._direct(slot, reqs[0])
         eng = self._engine(slot, bucket, reqs[0].params, len(reqs))
-        outs = [self.pool.get(r.shape) for r in reqs]
+        outs = [self.pool.get(r.shape, eng.stream) for r in reqs]
+        _wait_inputs(eng.stream, reqs)
         ev = eng.run([r.frame for r in reqs], outs)
         return ev, outs
 
@@ -436,7 +672,8 @@ class PerFrameExecutor(Executor):
                 with torch.cuda.stream(self.stream):
                     self.ws = _workspace(need, self.device)
                 self.ws_bytes = need
-            o = self.pool.get(r.shape)
+            o = self.pool.get(r.shape, self.stream)
+            _wait_inputs(self.stream, [r])
             L.check(lib.ipb_complete_ws(ctypes.c_void_p(r.frame.data_ptr()), H, W, ctypes.byref(cp),
                                         ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
                                         self.ws_bytes, h), "ipb_complete_ws")
@@ -444,6 +681,17 @@ class PerFrameExecutor(Executor):
         ev = torch.cuda.Event()
         ev.record(self.stream)
         return ev, outs
+
+    def submitted(self, req: Request) -> None:
+        _note_submit(req, self.device)
+
+    def resident_bytes(self) -> int:
+        return self.ws_bytes + self.pool.free_bytes
+
+    def trim(self, target: int) -> None:
+        self.pool.clear()
+        if self.resident_bytes() > target:
+            self.ws, self.ws_bytes = None, 0
 
     def ready(self, handle) -> bool:
         return handle[0].query()

@@ -61,7 +61,10 @@ def test_argument_checks_return_before_any_gpu_call():
     assert _ws_call(p, W=-3) == L.IPB_ERR_INVALID_ARG
     assert _ws_call(p, H=1 << 16, W=1 << 15) == L.IPB_ERR_INVALID_ARG        # H * W = 2^31
     assert _ws_call(p, H=(1 << 15) + 1, W=1 << 15) == L.IPB_ERR_INVALID_ARG  # H * W > 2^30
-    assert L.lib().ipb_workspace_bytes(1 << 15, 1 << 15, ctypes.byref(p)) > 0   # H * W = 2^30 is accepted
+    assert _ws_call(p, H=1 << 15, W=1 << 15) == L.IPB_ERR_INVALID_ARG        # H * W = 2^30
+    assert L.lib().ipb_workspace_bytes(1 << 15, 1 << 15, ctypes.byref(p)) == 0   # H * W = 2^30 is rejected
+    assert L.lib().ipb_workspace_bytes(1, (1 << 30) - 1, ctypes.byref(p)) > 0    # H * W = 2^30 - 1 is accepted
+    assert L.lib().ipb_workspace_bytes(3, 357913941, ctypes.byref(p)) > 0       # 2^30 - 1 = 3 * 357913941
     assert L.lib().ipb_workspace_bytes((1 << 15) + 1, 1 << 15, ctypes.byref(p)) == 0
     assert _ws_call(p, stage=0) == L.IPB_ERR_INVALID_ARG
     assert _ws_call(p, stage=10) == L.IPB_ERR_INVALID_ARG
@@ -196,6 +199,47 @@ def test_tile_table():
             assert lib.ipb_tile_shape(phase, t, ctypes.byref(r), ctypes.byref(c)) == 0
             assert r.value >= 8 and c.value >= 32
         assert lib.ipb_tile_shape(phase, n + 1, ctypes.byref(ctypes.c_int()), ctypes.byref(ctypes.c_int())) != 0
+
+
+def test_offsets_at_the_size_limit_on_host():
+    """The kernels' 32-bit byte offsets (offsets.hpp), compiled for the CPU:
+    at every accepted size up to the limit (H W = 2^30 - 1, several shapes)
+    the last cell's offset and the idle lanes' scratch slot past the map fit
+    in 32 bits, the slot lies past every cell, and H W = 2^30 is refused (its
+    slot offset would wrap to cell (0, 0))."""
+    src = r"""
+#include <cstdio>
+#include "offsets.hpp"
+int check(long long H, long long W) {
+  const bool ok = ipb::cells_ok((int)H, (int)W);
+  const bool want = H >= 1 && W >= 1 && H * W < (1LL << 30);
+  if (ok != want) { printf("cells_ok(%lld, %lld) = %d\n", H, W, ok); return 1; }
+  if (!ok) return 0;
+  const unsigned long long last = 4ULL * ((H - 1) * W + (W - 1));
+  const unsigned long long sink = 4ULL * H * W;
+  if (ipb::cell_offset((int)(H - 1), (int)(W - 1), (int)W) != last) { printf("cell %lld %lld\n", H, W); return 1; }
+  if (ipb::sink_offset((int)H, (int)W) != sink || sink >= (1ULL << 32) || sink <= last) {
+    printf("sink %lld %lld\n", H, W); return 1;
+  }
+  return 0;
+}
+int main() {
+  const long long M = (1LL << 30) - 1;   // 3 * 357913941 = 3^2 * 7 * 11 * 31 * 151 * 331
+  const long long shapes[][2] = {{1, M}, {M, 1}, {3, M / 3}, {M / 3, 3}, {9, M / 9}, {31 * 151, M / (31 * 151)},
+                                 {32767, 32769}, {32768, 32767}, {32768, 32768}, {32769, 32768}, {1, 1 << 30},
+                                 {1 << 30, 1}, {2, 1 << 29}, {1, 1}, {375, 1242}, {1024, 4096}, {0, 5}, {5, 0}};
+  int bad = 0;
+  for (auto& s : shapes) bad |= check(s[0], s[1]);
+  return bad;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        cpp = os.path.join(d, "t.cpp")
+        exe = os.path.join(d, "t")
+        with open(cpp, "w") as fh:
+            fh.write(src)
+        subprocess.run(["g++", "-O1", "-std=c++17", f"-I{CSRC}", cpp, "-o", exe], check=True)
+        assert subprocess.run([exe]).returncode == 0
 
 
 def test_median_network_on_host():

@@ -155,6 +155,113 @@ def test_served_results_equal_alone(executor):
         assert {len(eng.capacity) for eng in ex.engines.values()} <= {1, 4}
 
 
+@pytest.mark.parametrize("executor", ["graph", "per_frame"])
+def test_served_frames_produced_on_another_stream(executor):
+    """Frames copied to the device on a producer stream (behind a long
+    kernel there) and submitted right away, with no synchronisation: the
+    server orders its launches after the producer's work, so every result
+    equals the frame completed alone; outputs released by the client are
+    reused only after the client's stream is done with them."""
+    rng = np.random.default_rng(29)
+    shapes = [(352, 1216), (200, 640), (96, 333)]
+    host = []
+    for i in range(24):
+        H, W = shapes[i % len(shapes)]
+        m = synth.lidar_frame(H, W, seed=[29, i], n_rows=min(64, H), density=float(rng.uniform(0.03, 0.08))).sparse
+        host.append(torch.from_numpy(m).pin_memory())
+    if executor == "graph":
+        ex = serve.GraphExecutor(slots=3, max_batch=4)
+    else:
+        ex = serve.PerFrameExecutor()
+    srv = serve.Server(ex, mem_budget=256 << 20, max_batch=4 if executor == "graph" else 1)
+    producer = torch.cuda.Stream()
+    junk = torch.ones(32 << 20, device=DEV)
+    frames, reqs, copies = [], [], []
+    print(f"[serve {executor}] frames from a producer stream", flush=True)
+    with torch.cuda.stream(producer):
+        for i, h in enumerate(host):
+            junk.mul_(1.0)                               # keeps the producer stream busy ahead of the copy
+            d = h.to(DEV, non_blocking=True)
+            frames.append(d)
+            reqs.append(srv.submit(d))
+            srv.step()
+            done = [r for r in srv.done if r.out is not None and r.status == "done"]
+            for r in done:                               # the client reads an output on its stream, then releases it
+                copies.append((r.rid, r.out.clone()))
+                srv.release(r)
+    srv.drain()
+    torch.cuda.synchronize()
+    for r in srv.done:
+        if r.out is not None:
+            copies.append((r.rid, r.out.clone()))
+    torch.cuda.synchronize()
+    assert len(copies) == len(host) and all(r.status in ("done", "released") for r in reqs)
+    for rid, o in copies:
+        alone = api.complete(frames[rid])
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(o), bits(alone)), f"request {rid}"
+
+
+def test_complete_on_a_stream_other_than_the_current_one():
+    """api.complete / complete_batch on a non-current stream: buffers are
+    allocated under that stream and inputs recorded on it, so work queued
+    meanwhile on the current stream (allocating and freeing memory) cannot
+    take them over."""
+    f = lidar(375, 1242, [30, 0])
+    g = [lidar(200, 640, [30, 1]), lidar(96, 333, [30, 2])]
+    want = [bits(api.complete(x)) for x in [f] + g]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    junk = torch.ones(64 << 20, device=DEV)
+    with torch.cuda.stream(s):
+        junk.mul_(1.0)                                   # delays the calls below on s
+    out = api.complete(f, stream=s)
+    outs = api.complete_batch(g, stream=s)
+    for _ in range(8):                                   # churn of the current stream's allocations
+        t = torch.empty(4 * 375 * 1242 // 4 + 1024, device=DEV).fill_(-1.0)
+        del t
+    s.synchronize()
+    assert np.array_equal(bits(out), want[0])
+    for o, w in zip(outs, want[1:]):
+        assert np.array_equal(bits(o), w)
+
+
+def test_complete_batch_captured_into_a_graph():
+    """ipb_complete_batch allocates nothing and waits for nothing, so it can
+    be captured: replays of the captured call (with eager work and
+    synchronisations between them) equal the eager call and each frame
+    completed alone."""
+    import ctypes
+    shapes = [(375, 1242), (200, 640), (96, 333), (1, 7), (64, 64)]
+    frames = [lidar(H, W, [32, i]) for i, (H, W) in enumerate(shapes)]
+    # more descriptors than one upload chunk holds (the plan spans several launches)
+    frames += [lidar(40, 90, [32, 10 + i]) for i in range(60)]
+    outs = [torch.full_like(f, -1.0) for f in frames]
+    p = api.Params().to_c()
+    arr = api.frames_array(frames, outs)
+    lib = L.lib()
+    nb = int(lib.ipb_batch_workspace_bytes(arr, len(frames), ctypes.byref(p)))
+    ws = api._workspace(nb, frames[0].device)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        L.check(lib.ipb_complete_batch(arr, len(frames), ctypes.byref(p), ctypes.c_void_p(ws.data_ptr()), nb,
+                                       ctypes.c_void_p(s.cuda_stream)), "ipb_complete_batch")
+    want = [bits(api.complete(f)) for f in frames]
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device=DEV)
+        junk.mul_(2.0).sum().item()
+        for i, (o, w) in enumerate(zip(outs, want)):
+            assert np.array_equal(bits(o), w), f"replay {rep} frame {i} {tuple(frames[i].shape)}"
+
+
 def test_quality_sweep_runs_every_design_step():
     from paper_1802_00036_amd import quality
     frames = [synth.lidar_frame(120, 300, seed=[24, i], n_rows=40, density=0.05) for i in range(2)]
@@ -300,20 +407,24 @@ def test_batches_in_flight_on_streams():
 
 @pytest.mark.parametrize("cfg", [2, 4])
 def test_bench_configuration_full_batch(cfg):
-    """The whole batch the bench times (64 x 375x1242; 16 x 1024x4096 with the
-    tiles the autotuner picks for it), in the bench's launch configuration:
-    every frame bitwise equal to the frame completed alone, and frames spread
-    over the batch equal to the oracle."""
+    """The whole batch the bench times (64 x 375x1242; 16 x 1024x4096) with
+    the tiles the bench takes for it (the shipped tuning table's entry for
+    three streams, as on a box without a user cache), in the bench's launch
+    configuration: every frame bitwise equal to the frame completed alone,
+    and frames spread over the batch equal to the oracle."""
+    from paper_1802_00036_amd import autotune
     p = api.Params(max_depth=140.0) if cfg == 4 else api.Params()
-    if cfg == 4:
-        p = dataclasses.replace(p, tile_local=5, tile_global=5)
     fr = synth.config_frames(cfg)
     frames = [torch.from_numpy(f.sparse).to(DEV) for f in fr]
+    tuned = autotune.lookup(frames, p, streams=3, user_cache=False)
+    assert tuned is not None, f"the shipped tuning table has no entry for c{cfg}"
+    p = tuned
     outs = [torch.empty_like(t) for t in frames]
-    print(f"[bench config c{cfg}] {len(frames)} frames", flush=True)
+    print(f"[bench config c{cfg}] {len(frames)} frames, tiles {p.tile_local}/{p.tile_global}", flush=True)
     _planned_steps(frames, outs, p)
+    alone = dataclasses.replace(p, tile_local=0, tile_global=0)   # the library's tiles for one frame
     for i, (t, o) in enumerate(zip(frames, outs)):
-        assert np.array_equal(bits(o), bits(api.complete(t, p))), f"c{cfg} frame {i}: batch != alone"
+        assert np.array_equal(bits(o), bits(api.complete(t, alone))), f"c{cfg} frame {i}: batch != alone"
     sample = [0, len(fr) // 2, len(fr) - 1] if cfg == 4 else [0, 9, 21, 33, 47, 63]
     for i in sample:
         want = oracle.complete_map(fr[i].sparse, oracle.Params(max_depth=p.max_depth))

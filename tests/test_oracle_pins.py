@@ -26,9 +26,9 @@ def same_bits(a, b):
     return np.array_equal(bits(a), bits(b))
 
 
-def load_blocks(name):
+def load_blocks(name, dtype=F32):
     """Fixture files: '# comment' lines, then 'input H W' / 'expected H W'
-    blocks of whitespace-separated rows."""
+    blocks of whitespace-separated rows (expected values read as dtype)."""
     blocks, cur = [], None
     with open(os.path.join(GOLDEN, name)) as fh:
         lines = [ln.strip() for ln in fh if ln.strip() and not ln.startswith("# ")]
@@ -37,7 +37,7 @@ def load_blocks(name):
         tag, h, w = lines[i].split()
         h, w = int(h), int(w)
         rows = [[float(t) for t in lines[i + 1 + k].split()] for k in range(h)]
-        blocks.append((tag, np.array(rows, F32).reshape(h, w)))
+        blocks.append((tag, np.array(rows, F32 if tag == "input" else dtype).reshape(h, w)))
         i += 1 + h
     return [(blocks[k][1], blocks[k + 1][1]) for k in range(0, len(blocks), 2)]
 
@@ -90,6 +90,16 @@ def test_golden_gauss():
     for inp, exp in load_blocks("gauss_rows.txt"):
         g = oracle.gaussian_sum(inp, 5, 0.0)
         assert np.array_equal(g, exp.astype(np.float64))
+
+
+def test_golden_bilateral():
+    """Hand-derived closed forms of the bilateral blur on a row and a column
+    (sigma_space 1, sigma_color 2): pins the range scale 1 / (2 sigma_c^2),
+    the spatial scale and the reflect-101 taps independently of the brute
+    force, which restates the same formula."""
+    for inp, exp in load_blocks("bilateral3.txt", np.float64):
+        got = O.bilateral_sum(inp, 3, 1.0, 2.0)
+        assert np.allclose(got, exp, rtol=1e-13, atol=0.0), (got, exp)
 
 
 # -------------------------------------------------------------- brute force --
@@ -502,6 +512,19 @@ def test_bilateral_and_limit_pins_catch_planted_mistakes(monkeypatch):
     def no_range(v, size, ss, sc):
         return O.gaussian_sum(v, size, ss)
     assert _pins_fail(monkeypatch, "bilateral_sum", no_range, [test_bilateral_closed_forms]) >= 1
+
+    # the range scale off by a factor of two (1 / sigma_c^2): only the
+    # hand-derived fixture sees it (every closed form above is a limit)
+    real = O.bilateral_sum
+
+    def half_scale(v, size, ss, sc):
+        return real(v, size, ss, float(np.sqrt(0.5) * sc))
+    assert _pins_fail(monkeypatch, "bilateral_sum", half_scale, [test_golden_bilateral]) >= 1
+
+    # the spatial scale off by a factor of two
+    def bad_space(v, size, ss, sc):
+        return real(v, size, float(np.sqrt(0.5) * ss), sc)
+    assert _pins_fail(monkeypatch, "bilateral_sum", bad_space, [test_golden_bilateral]) >= 1
 
     # the limit off by one row
     def bad_limit(v, p):

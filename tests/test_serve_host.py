@@ -252,3 +252,166 @@ def test_graph_batch_tile_rule_matches_the_library(shapes, chain):
     assert lib_bytes == max(explicit, default)
     if chain == "median3":
         assert picked.tile_global == 0                  # 16- and 8-row phase-2 tiles: 5x5 median chains only
+
+
+# ------------------------------------------------------- failure handling --
+
+class FailingExecutor(FakeExecutor):
+    """Launches whose requests include a rid in `bad_launch` raise at
+    launch; batches holding a rid in `bad_done` raise when polled.  A set
+    entry "alone" fails only when the request runs alone, "batch" only in a
+    batch of several, "always" both times."""
+
+    def __init__(self, bad_launch=None, bad_done=None, **kw):
+        super().__init__(**kw)
+        self.bad_launch = bad_launch or {}
+        self.bad_done = bad_done or {}
+        self.attempts = collections.Counter()
+
+    @staticmethod
+    def _hit(table, reqs):
+        for r in reqs:
+            mode = table.get(r.rid)
+            if mode == "always" or (mode == "alone" and len(reqs) == 1) or (mode == "batch" and len(reqs) > 1):
+                return True
+        return False
+
+    def launch(self, slot, bucket, reqs):
+        for r in reqs:
+            self.attempts[r.rid] += 1
+        if self._hit(self.bad_launch, reqs):
+            raise RuntimeError("launch failed")
+        h = super().launch(slot, bucket, reqs)
+        h["fail"] = self._hit(self.bad_done, reqs)
+        return h
+
+    def ready(self, h):
+        ok = super().ready(h)
+        if ok and h["fail"]:
+            raise RuntimeError("device fault reported at completion")
+        return ok
+
+
+def _failing_server(**kw):
+    ex = FailingExecutor(slots=2, polls=2, **kw)
+    return serve.Server(ex, mem_budget=10**9, max_batch=4, clock=FakeClock()), ex
+
+
+def test_failed_batch_is_retried_alone_once():
+    """A batch whose launch raises (request 2 poisons any batch it is in):
+    every request of it is retried alone; those that then succeed complete,
+    and no request is launched more than twice."""
+    srv, ex = _failing_server(bad_launch={2: "batch"})
+    reqs = [srv.submit(Frame(64, 64, i)) for i in range(4)]
+    srv.drain()
+    assert all(r.status == "done" for r in reqs)
+    assert srv.failed_batches == 1
+    assert all(ex.attempts[r.rid] == 2 for r in reqs)
+    assert all(r.solo for r in reqs)
+    assert srv.in_use == sum(r.nbytes for r in reqs)
+
+
+def test_request_failing_alone_is_marked_failed():
+    """Request 1 fails every time: after its batch fails and its solo retry
+    fails, it is marked failed with the error; its memory leaves the budget
+    and the others complete."""
+    srv, ex = _failing_server(bad_launch={1: "always"})
+    reqs = [srv.submit(Frame(64, 64, i)) for i in range(3)]
+    srv.drain()
+    assert [r.status for r in reqs] == ["done", "failed", "done"]
+    assert "launch failed" in reqs[1].error
+    assert ex.attempts[1] == 2
+    assert srv.failed == [reqs[1]]
+    assert srv.in_use == reqs[0].nbytes + reqs[2].nbytes
+    assert srv.stats()["failed"] == 1
+
+
+def test_failure_reported_at_completion_is_retried():
+    """The device work of a batch fails (the end-of-batch query raises): the
+    slot is freed, the batch's requests are retried alone, a lone request
+    failing on its own is marked failed."""
+    srv, ex = _failing_server(bad_done={0: "batch", 3: "always"})
+    reqs = [srv.submit(Frame(64, 64, i)) for i in range(4)]
+    srv.drain()
+    assert [r.status for r in reqs] == ["done", "done", "done", "failed"]
+    assert "device fault" in reqs[3].error
+    assert sorted(srv.free_slots) == [0, 1]
+    assert srv.idle()
+
+
+def test_lone_request_failing_gets_one_retry():
+    srv, ex = _failing_server(bad_launch={0: "always"})
+    r = srv.submit(Frame(64, 64, 0))
+    srv.drain()
+    assert r.status == "failed" and ex.attempts[0] == 2
+
+
+def test_cancel_in_every_state():
+    srv, ex = make_server(slots=1, polls=5, max_batch=1, budget=3 * 4 * 64 * 64)
+    reqs = [srv.submit(Frame(64, 64, i)) for i in range(6)]
+    srv.step()                      # r0 runs, r1 and r2 are admitted, r3.. wait for memory
+    assert [r.status for r in reqs[:4]] == ["running", "admitted", "admitted", "queued"]
+    assert srv.cancel(reqs[3]) and reqs[3].status == "cancelled"       # waiting
+    assert srv.cancel(reqs[1]) and reqs[1].status == "cancelled"       # admitted: its bytes leave
+    assert srv.in_use == 2 * 4 * 64 * 64
+    assert srv.cancel(reqs[0]) and reqs[0].status == "running"         # running: marked only
+    srv.drain()
+    assert reqs[0].status == "cancelled" and reqs[0].out is None
+    assert [r.status for r in reqs[2:]] == ["done", "cancelled", "done", "done"]
+    assert not srv.cancel(reqs[2])                                     # already finished
+    assert srv.in_use == sum(r.nbytes for r in (reqs[2], reqs[4], reqs[5]))
+    assert ex.recycled == 1                                            # r0's buffer went back
+    assert {r.rid for r in srv.done} == {2, 4, 5}
+
+
+def test_requests_time_out_before_launch():
+    """With one slot held by a long batch, requests still waiting or admitted
+    past their deadline time out (their bytes leave the budget); a running
+    batch is never timed out; a request with its own longer timeout stays."""
+    clock = FakeClock(step=1e-3)
+    ex = FakeExecutor(slots=1, polls=40)
+    srv = serve.Server(ex, mem_budget=10**9, max_batch=1, clock=clock, timeout=0.01)
+    first = srv.submit(Frame(64, 64, 0))
+    srv.step()
+    late = [srv.submit(Frame(64, 64, i)) for i in range(1, 4)]
+    patient = srv.submit(Frame(64, 64, 9), timeout=10.0)
+    srv.step()                        # admitted, waiting for the slot
+    for _ in range(30):
+        srv.step()
+    assert first.status in ("running", "done")
+    assert all(r.status == "timeout" for r in late)
+    srv.drain()
+    assert first.status == "done" and patient.status == "done"
+    assert srv.in_use == first.nbytes + patient.nbytes
+    assert srv.stats()["timed_out"] == 3
+
+
+class ResidentExecutor(FakeExecutor):
+    """Holds `held` bytes of resident memory that trim() can drop."""
+
+    def __init__(self, held, **kw):
+        super().__init__(**kw)
+        self.held = held
+        self.trims = []
+
+    def resident_bytes(self):
+        return self.held
+
+    def trim(self, target):
+        self.trims.append(target)
+        self.held = min(self.held, target)
+
+
+def test_admission_counts_resident_memory():
+    fb = 4 * 64 * 64
+    ex = ResidentExecutor(held=3 * fb, slots=1, polls=3)
+    srv = serve.Server(ex, mem_budget=5 * fb, max_batch=8, clock=FakeClock())
+    reqs = [srv.submit(Frame(64, 64, i)) for i in range(4)]
+    srv.step()
+    # 3 frames' worth is resident: only two outputs fit beside it
+    assert sum(r.status in ("admitted", "running") for r in reqs) == 2
+    srv.drain()
+    assert all(r.status == "done" for r in reqs)
+    # the last two could only be admitted after trim() dropped idle memory
+    # (outputs of the first two are kept, so 2 frames + 2 frames leave 1)
+    assert ex.trims and ex.held <= fb
