@@ -54,7 +54,9 @@ typedef enum {
   IPB_ERR_INVALID_ARG = -1,   /* null pointer, bad size, bad parameter, overlap  */
   IPB_ERR_UNSUPPORTED = -2,   /* a parameter value outside what the kernels hold */
   IPB_ERR_WORKSPACE = -3,     /* workspace missing or smaller than required      */
-  IPB_ERR_HIP = -4            /* a HIP call failed; see ipb_last_hip_error()     */
+  IPB_ERR_HIP = -4,           /* a HIP call failed; see ipb_last_hip_error()     */
+  IPB_ERR_SCRATCH = -5        /* ipb_complete_static: frame too large for the
+                                 static scratch                                  */
 } ipb_status;
 
 /* Kernel shapes compared in Sec. IV "Custom Kernel Design" (Table 2).  The
@@ -134,6 +136,24 @@ int ipb_complete(const float* depth_in, int H, int W, const ipb_params* p,
  * synchronises nothing. */
 int ipb_complete_ws(const float* depth_in, int H, int W, const ipb_params* p,
                     float* depth_out, void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory at all (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * ipb_complete_ws with the library's own static device array of
+ * IPB_STATIC_SCRATCH_BYTES as the workspace, one per GPU, held until the
+ * process ends.  Allocates nothing (no hipMalloc, no allocating library
+ * call; the array's device address is looked up once per device on the
+ * first call there) and synchronises nothing.  Frames whose workspace
+ * (ipb_workspace_bytes) exceeds the array return IPB_ERR_SCRATCH before
+ * anything is enqueued: 1024 x 4096 fits with the default parameters.  The
+ * array keeps the last call's contents; each call clears what must start
+ * at zero.  Every call on a GPU shares that GPU's array: calls that overlap
+ * in time on one GPU (on different streams, or from different threads with
+ * no stream order between them) race and give wrong results; order them on
+ * one stream. */
+#define IPB_STATIC_SCRATCH_BYTES ((size_t)48 << 20)
+int ipb_complete_static(const float* depth_in, int H, int W, const ipb_params* p,
+                        float* depth_out, void* stream);
 
 /* Test hook: run stages 1..last_stage (1 <= last_stage <= 9) and write the map
  * of stage last_stage to out (see the stage list above).  Same workspace rule

@@ -17,6 +17,7 @@ IPB_ERR_INVALID_ARG = -1
 IPB_ERR_UNSUPPORTED = -2
 IPB_ERR_WORKSPACE = -3
 IPB_ERR_HIP = -4
+IPB_ERR_SCRATCH = -5
 
 
 class CParams(ctypes.Structure):
@@ -70,6 +71,8 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_void_p]),
     "ipb_complete_ws": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _P(CParams),
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "ipb_complete_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _P(CParams),
+                                           ctypes.c_void_p, ctypes.c_void_p]),
     "ipb_complete_stage": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _P(CParams),
                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.c_void_p]),

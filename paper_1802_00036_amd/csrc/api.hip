@@ -240,6 +240,28 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 // kernels take it by value; grown as needed, reused by the calling thread.
 thread_local std::vector<int32_t> t_plan;
 
+// Workspace of ipb_complete_static: a fixed device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it only stands for the symbol):
+// the device address comes from hipGetSymbolAddress, once per device with
+// that device current, and is kept per device.
+static __device__ __align__(256) unsigned char scratch[IPB_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+int static_scratch(int dev, void** out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (ptr == nullptr || (reinterpret_cast<uintptr_t>(ptr) % kAlign) != 0) return hip_fail(hipErrorInvalidSymbol);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return IPB_OK;
+}
+
 // Fill a plan (host memory) for frames whose workspace is ws.
 void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, void* plan_host) {
   auto* hdr = static_cast<PlanHeader*>(plan_host);
@@ -542,6 +564,25 @@ int ipb_complete(const float* depth_in, int H, int W, const ipb_params* p, float
   return IPB_OK;
 }
 
+int ipb_complete_static(const float* depth_in, int H, int W, const ipb_params* p, float* depth_out,
+                        void* stream) {
+  Resolved r;
+  int st = resolve_single(p, H, W, &r);
+  if (st != IPB_OK) return st;
+  if (depth_in == nullptr || depth_out == nullptr || !size_ok(H, W)) return IPB_ERR_INVALID_ARG;
+  if (frame_ws_bytes(H, W, r) > (size_t)IPB_STATIC_SCRATCH_BYTES) return IPB_ERR_SCRATCH;
+  int dev = 0;
+  st = device_cus(&dev);                 // the current device (no allocation)
+  if (st != IPB_OK) return st;
+  void* ws = nullptr;
+  st = static_scratch(dev, &ws);
+  if (st != IPB_OK) return st;
+  // the reset step of the chain clears what must start at zero (column
+  // tops, queue counters); everything else is written before it is read
+  return run_single(depth_in, H, W, p, depth_out, 9, ws, (size_t)IPB_STATIC_SCRATCH_BYTES,
+                    static_cast<hipStream_t>(stream));
+}
+
 size_t ipb_batch_plan_bytes(int n) {
   if (n < 1) return 0;
   return sizeof(PlanHeader) + sizeof(FrameDesc) * (size_t)n;
@@ -636,6 +677,7 @@ const char* ipb_status_string(int status) {
     case IPB_ERR_UNSUPPORTED: return "unsupported parameter value";
     case IPB_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case IPB_ERR_HIP: return "HIP runtime error";
+    case IPB_ERR_SCRATCH: return "frame needs more workspace than the static scratch holds";
     default: return "unknown status";
   }
 }

@@ -44,7 +44,7 @@ def test_params_default_is_the_paper_design():
 
 
 def test_status_strings():
-    for st in (0, -1, -2, -3, -4, 7):
+    for st in (0, -1, -2, -3, -4, -5, 7):
         assert isinstance(L.status_string(st), str)
 
 
@@ -66,6 +66,13 @@ def test_argument_checks_return_before_any_gpu_call():
     assert L.lib().ipb_workspace_bytes(1, (1 << 30) - 1, ctypes.byref(p)) > 0    # H * W = 2^30 - 1 is accepted
     assert L.lib().ipb_workspace_bytes(3, 357913941, ctypes.byref(p)) > 0       # 2^30 - 1 = 3 * 357913941
     assert L.lib().ipb_workspace_bytes((1 << 15) + 1, 1 << 15, ctypes.byref(p)) == 0
+    # the static-scratch entry point refuses frames whose workspace exceeds its
+    # array before touching the GPU
+    static = L.lib().ipb_complete_static
+    assert static(ctypes.c_void_p(FAKE), 4096, 4096, ctypes.byref(p), ctypes.c_void_p(FAKE + (1 << 30) * 3),
+                  None) == L.IPB_ERR_SCRATCH
+    assert static(ctypes.c_void_p(0), 64, 64, ctypes.byref(p), ctypes.c_void_p(FAKE), None) == L.IPB_ERR_INVALID_ARG
+    assert L.lib().ipb_workspace_bytes(1024, 4096, ctypes.byref(p)) <= 48 << 20   # the largest serving frame fits
     assert _ws_call(p, stage=0) == L.IPB_ERR_INVALID_ARG
     assert _ws_call(p, stage=10) == L.IPB_ERR_INVALID_ARG
     assert _ws_call(p, ws=0) == L.IPB_ERR_WORKSPACE
