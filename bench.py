@@ -37,13 +37,14 @@ METRIC = "frames/s and HBM GB/s at 375x1242 batched; p50/p99 latency under servi
 HBM_PEAK_GBPS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # non-packed 32-bit VALU lane-operations
 # launch steps of one batch (ipb_complete_planned phases 0..5) and the kernels each launches
-PHASES = ["k_reset", "k_local_stream", "k_fill_scan+k_fill_tiles", "k_global_stream",
+PHASES = ["k_reset", "k_local_stream", "k_fill_scan+k_fill_tiles", "k_global_rows",
           "k_fill_cells+k_fill_dense+k_global_patched", "k_global_slow"]
 # algorithmic HBM bytes per pixel: stage-1 input read + stage-4 map write (phase 1);
 # stage-4 map read + output write (phase 2)
-BYTES_PER_PX = {"k_local_stream": 8, "k_global_stream": 8}
+BYTES_PER_PX = {"k_local_stream": 8, "k_global_rows": 8}
 CSRC = os.path.join(ROOT, "paper_1802_00036_amd", "csrc")
-KERNEL_SOURCES = ("common.hpp", "networks.hpp", "median_net.hpp", "offsets.hpp", "kernels.hip", "stream.hip",
+KERNEL_SOURCES = ("common.hpp", "networks.hpp", "median_net.hpp", "median_rows.hpp", "offsets.hpp", "kernels.hip",
+                  "stream.hip",
                   "api.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_batched.json")
 PARAMS_TEXT = "diamond5 close5 fill7 extend fill31 median5 gauss5(binomial)"
@@ -508,13 +509,15 @@ def serving_runs(host_pool, rates, seconds, modes=("batched", "per_frame"), warm
             arrivals, sizes = synth.poisson_arrivals(rate, n)
             frames = [pool[int(s)][i % len(pool[int(s)])] for i, s in enumerate(sizes)]
             params = [p140 if int(s) in big else None for s in sizes]
+            # the pool's frames were made and synchronised before the trace
+            # starts: launches need not wait for the stream they came from
             if mode == "batched":
-                ex = serve.GraphExecutor(slots=3, max_batch=16)
+                ex = serve.GraphExecutor(slots=3, max_batch=16, order_inputs=False)
                 ex.warm([((serve.default_bucket(synth.SERVE_SIZES[s]), serve._params_key(p140 if s in big else None)),
                           p140 if s in big else None) for s in range(len(synth.SERVE_SIZES))])
                 srv = serve.Server(ex, mem_budget=budget, max_batch=16, keep_outputs=False)
             else:
-                ex = serve.PerFrameExecutor()
+                ex = serve.PerFrameExecutor(order_inputs=False)
                 srv = serve.Server(ex, mem_budget=budget, max_batch=1, keep_outputs=False)
                 for s in range(len(synth.SERVE_SIZES)):
                     api.complete(pool[s][0], p140 if s in big else None)

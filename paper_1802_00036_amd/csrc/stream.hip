@@ -13,10 +13,13 @@
 //                     records and the final tops give the cells that are
 //                     empty after the extension; their 31x31 fill goes into
 //                     the stage-4 map, tagged.
-//   k_global_stream : stages 5, 7, 8, 9 (extension on load, 5x5 median,
-//                     Gaussian, output inversion); 128 input columns -> 120
-//                     output columns.  Default chain: reads the filled map.
-//                     Other chains: a tile whose needed cells still hold an
+//   k_global_rows   : stages 5, 7, 8, 9 of the default chain (extension on
+//                     load, 5x5 median, Gaussian, output inversion) on the
+//                     filled map, two rows per step, the median sorting rows
+//                     first; 128 input columns -> 120 output columns.
+//   k_global_stream : the same stages for other chains, one row per step,
+//                     the median sorting columns first.  A tile whose
+//                     needed cells still hold an
 //                     empty pixel after the extension needs the 31x31 fill
 //                     (stage 6): its quarters are queued, and the empty
 //                     cells of quarters with few of them are queued one by
@@ -33,6 +36,7 @@
 #include <utility>
 
 #include "common.hpp"
+#include "median_rows.hpp"
 #include "networks.hpp"
 #include "offsets.hpp"
 
@@ -412,17 +416,15 @@ __device__ __forceinline__ double hsum5(double wc, double w1, double w2, int m2,
   return fma(wc, (double)val(c), fma(w1, s1, w2 * s2));
 }
 
-// Stages 5-9 of one streaming tile (TH x 120 output cells).
-// FAST (the default chain): the fill of stage 6 already ran (k_fill_scan,
-// k_fill_tiles) and wrote its values into the stage-4 map, tagged; the pass
-// reads stage-6 values directly.
-// Otherwise, first pass (PATCHED false): the stage-6 map is taken to equal
+// Stages 5-9 of one streaming tile (TH x 120 output cells) for chains other
+// than the default one (which takes rows_first_tile).
+// First pass (PATCHED false): the stage-6 map is taken to equal
 // the stage-5 map; tiles where that does not hold are queued by quarter.
 // Second pass (PATCHED true, one quarter): cells empty after stage 5 read
 // their stage-6 value from f.v6p (written by k_fill_cells / k_fill_dense).
 // s_cells: LDS lists of the first kCellEmpty empty cells of each quarter
 // (first pass only).
-template <int TH, bool PATCHED, bool FAST, bool INTERIOR = false>
+template <int TH, bool PATCHED>
 __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KParams& kp, int t, int fidx, int gt,
                                                    int ty0, int tx0, int lane, int32_t* slow, int cap, int* s_cells) {
   const int H = f.H, W = f.W;
@@ -484,9 +486,8 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
     selb = (sb & 1) != 0;
   }
 
-  // FAST: the binomial taps (1 4 6 4 1)/16 as constants
-  const double wc = FAST ? 6.0 : kp.gw[0], w1 = FAST ? 4.0 : kp.gw[1], w2 = FAST ? 1.0 : kp.gw[2];
-  const double gsc = FAST ? 1.0 / 256.0 : kp.gscale;
+  const double wc = kp.gw[0], w1 = kp.gw[1], w2 = kp.gw[2];
+  const double gsc = kp.gscale;
   const int q0 = ty0 - 4;
   const int n = TH + 8;
   int raw[8][2];         // stage-5 keys (window of the median)
@@ -515,13 +516,8 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
   auto fetch = [&](int r, int u_) {
     const unsigned rowoff = (unsigned)clampi_s(q0 + r, 0, H - 1) * W4;
     unsigned oa_ = rowoff + oxa, ob_ = rowoff + oxb;
-    if constexpr (FAST) {
-      oa_ = max(oa_, toffa);
-      ob_ = max(ob_, toffb);
-    } else {
-      oa_ = (oa_ < toffa && oa_ >= tlima) ? toffa : oa_;
-      ob_ = (ob_ < toffb && ob_ >= tlimb) ? toffb : ob_;
-    }
+    oa_ = (oa_ < toffa && oa_ >= tlima) ? toffa : oa_;
+    ob_ = (ob_ < toffb && ob_ >= tlimb) ? toffb : ob_;
     pa[u_] = ldk(v4, oa_);
     pb[u_] = ldk(v4, ob_);
     if (PATCHED) {
@@ -533,30 +529,19 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
   for (int u = 0; u < 4; ++u) fetch(u, u);
 
   // One row step: row q = q0 + r enters, the median of row q - 2 and the
-  // outputs of row q - 4 leave.  FAST: the default chain (5x5 median, 5x5
-  // Gaussian, every stage); rows outside the frame are the replicated
-  // border rows the loads already give (the median's border rule), so only
-  // the Gaussian's reflected rows and the output rows need checks.
+  // outputs of row q - 4 leave.
   auto step = [&](auto u_tag, const int r, auto warm_tag) __attribute__((always_inline)) {
     constexpr int u = decltype(u_tag)::value;            // ring slot: a constant
     constexpr bool WARM = decltype(warm_tag)::value;     // the first block: r = u
     const int q = q0 + r;
-    // FAST: cells the fill ahead of this pass completed carry kFillTag
-    int va, vb;
-    if constexpr (FAST) {
-      va = pa[u & 3] & ~kFillTag;
-      vb = pb[u & 3] & ~kFillTag;
-    } else {
-      va = detach(pa[u & 3]);
-      vb = detach(pb[u & 3]);
-    }
+    int va = detach(pa[u & 3]), vb = detach(pb[u & 3]);
     if (PATCHED) {
       va = va <= kthr ? detach(ppa[u & 3]) : va;
       vb = vb <= kthr ? detach(ppb[u & 3]) : vb;
     }
     fetch(r + 4, u & 3);
-    if (FAST || (q >= 0 && q < H)) {
-      if (!FAST && !PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
+    if (q >= 0 && q < H) {
+      if (!PATCHED && __ballot((ina && va <= kthr) || (inb && vb <= kthr)) != 0) {
         // row q is an input row of quarter k when k*QR - 4 <= q - ty0 < (k+1)*QR + 4
         const int rel = q - ty0;
 #pragma unroll
@@ -582,13 +567,13 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
             if (kk == k) qempty[kk] += n_e;
         }
       }
-      if (!FAST && (last == 5 || last == 6) && q >= ty0 && q < ty0 + TH) {
+      if ((last == 5 || last == 6) && q >= ty0 && q < ty0 + TH) {
         const unsigned ro = (unsigned)q * W4;
         if (outa) stk(out, ro + ua, va);
         if (outb) stk(out, ro + ub, vb);
       }
     }
-    if (FAST || median) {
+    if (median) {
       window_update(Sa, raw[(u - 5) & 7][0], va);
       window_update(Sb, raw[(u - 5) & 7][1], vb);
     }
@@ -599,7 +584,7 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
     // Stage 7: median of row m = q - 2.
     const int m = q - 2;
     int v7a, v7b;
-    if (FAST || median) {
+    if (median) {
       int Lb[5], La[5], Rb[5], m1[10], m2[10], core[6];
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
@@ -625,20 +610,19 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
     }
     s7[u][0] = v7a;
     s7[u][1] = v7b;
-    if (!FAST && last == 7 && m >= ty0 && m < ty0 + TH && m < H && m >= 0) {
+    if (last == 7 && m >= ty0 && m < ty0 + TH && m < H && m >= 0) {
       const unsigned ro = (unsigned)m * W4;
       if (outa) stk(out, ro + ua, v7a);
       if (outb) stk(out, ro + ub, v7b);
     }
 
     // Stage 8: horizontal sums of row m (reflect-101 rows are copies).
-    if (FAST || (m >= 0 && m < H)) {
+    if (m >= 0 && m < H) {
       const int La = from_prev(v7a), Lb = from_prev(v7b), Ra = from_next(v7a), Rb = from_next(v7b);
       hs[u][0] = hsum5(wc, w1, w2, La, Lb, v7a, v7b, Ra);
       hs[u][1] = hsum5(wc, w1, w2, Lb, v7a, v7b, Ra, Rb);
     }
-    if (INTERIOR) {                             // no border row among the tile's rows
-    } else if (m == 2 && q0 + 2 <= 0) {         // rows -1, -2 mirror rows 1, 2
+    if (m == 2 && q0 + 2 <= 0) {         // rows -1, -2 mirror rows 1, 2
       hs[(u - 3) & 7][0] = hs[(u - 1) & 7][0];
       hs[(u - 3) & 7][1] = hs[(u - 1) & 7][1];
       hs[(u - 4) & 7][0] = hs[u][0];
@@ -654,11 +638,11 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
 
     // Stages 8 and 9 for row g = q - 4.
     const int g = q - 4;
-    if (FAST ? (INTERIOR || g < H) : (g >= ty0 && g < ty0 + TH && g < H && last >= 8)) {
+    if (g >= ty0 && g < ty0 + TH && g < H && last >= 8) {
       const int ca7 = s7[(u - 2) & 7][0], cb7 = s7[(u - 2) & 7][1];
       const bool ma = ca7 > kthr, mb = cb7 > kthr;
       float oa, ob;
-      if (FAST || kp.rg > 0) {
+      if (kp.rg > 0) {
         const double ga = fma(wc, hs[(u - 2) & 7][0],
                               fma(w1, hs[(u - 3) & 7][0] + hs[(u - 1) & 7][0],
                                   w2 * (hs[(u - 4) & 7][0] + hs[u][0])));
@@ -671,7 +655,7 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
         oa = ma ? val(ca7) : 0.f;
         ob = mb ? val(cb7) : 0.f;
       }
-      if (FAST || last == 9) {
+      if (last == 9) {
         oa = ma ? off - oa : 0.f;
         ob = mb ? off - ob : 0.f;
       }
@@ -744,7 +728,223 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
 }
 
 
-template <int TH, bool FAST>
+// Stages 5, 7, 8 and 9 of one streaming tile of the default chain (TH x 120
+// output cells), two rows per step.  The 31x31 fill of stage 6 already ran
+// ahead of this pass and left its values, tagged, in the stage-4 map.
+//
+// The median sorts rows first.  Each input row's 5-wide windows are sorted
+// across the lane's two columns and its neighbours' (mr::row_windows); an
+// output's five sorted row windows are then merged down the rows in
+// registers.  A step takes input rows q and q + 1 and gives the medians of
+// rows q - 2 and q - 1, which share rows q - 3 .. q: the pair merges of rows
+// (q - 3, q - 2) (from the step before) and (q - 1, q), and ranks 7..12 of
+// those 20 values; each median adds its fifth row (q - 4 or q + 1) to them.
+// The Gaussian's horizontal sums of the two median rows go to a ring, and the
+// outputs of rows q - 4 and q - 3 leave with their vertical sums.
+//
+// Rows outside the frame are the replicated border rows the clamped loads
+// give (the median's border rule); the Gaussian's reflected rows (-1, -2
+// and H, H + 1) are copies of its sums of rows 1, 2 and H - 2, H - 3, and
+// its reflected columns come from the lanes that hold them.  INTERIOR tiles
+// need none of these rows.
+template <int TH, bool INTERIOR>
+__device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParams& kp, int ty0, int tx0, int lane) {
+  static_assert(TH % 8 == 0, "tile rows");
+  const int H = f.H, W = f.W;
+  const float off = kp.off;
+  const int kthr = key(kp.thr);
+  const int ca = tx0 - 4 + 2 * lane, cb = ca + 1;
+  const int xa = clampi_s(ca, 0, W - 1), xb = clampi_s(cb, 0, W - 1);     // replicated border columns
+  const unsigned oxa = 4u * (unsigned)xa, oxb = 4u * (unsigned)xb;
+  const bool ina = ca >= 0 && ca < W, inb = cb >= 0 && cb < W;
+  const bool lane_out = lane >= 2 && lane < 62;
+  const bool outa = lane_out && ina, outb = lane_out && inb;
+  const unsigned ua = 4u * (unsigned)ca, ub = ua + 4u;   // byte offsets, used only when in the image
+  const bool edge_cols = tx0 - 4 < 0 || tx0 + kGlobalTW + 4 > W;
+  gcint* v4 = gc(f.v4);
+  gint* out = gw(f.out);
+  const unsigned W4 = 4u * (unsigned)W;
+  // Stage 5 on load: a row above its column's top reads the top cell,
+  // V5[y][x] = V4[max(y, top)][x]; as byte offsets, the larger of the row's
+  // and the top cell's (0 without a top or without the extension).
+  unsigned toffa = 0, toffb = 0;
+  if (kp.extrapolate) {
+    gcint* top = gc(f.top);
+    const int t_a = top[xa], t_b = top[xb];
+    if (t_a < H) toffa = (unsigned)t_a * W4 + oxa;
+    if (t_b < H) toffb = (unsigned)t_b * W4 + oxb;
+  }
+  // reflect-101 source lane/slot of this lane's columns, for the Gaussian's border
+  int sla = 0, slb = 0;
+  bool sela = false, selb = false;
+  if (edge_cols) {
+    auto refl = [&](int c) {
+      if (c < 0) c = -c;
+      if (c >= W) c = 2 * W - 2 - c;
+      return c;
+    };
+    const int sa = refl(ca) - (tx0 - 4), sb = refl(cb) - (tx0 - 4);
+    sla = clampi_s(sa >> 1, 0, kLanes - 1);
+    slb = clampi_s(sb >> 1, 0, kLanes - 1);
+    sela = (sa & 1) != 0;
+    selb = (sb & 1) != 0;
+  }
+  const int q0 = ty0 - 4;              // first input row; step s takes rows q0 + 2s, q0 + 2s + 1
+
+  int Fw[2][2][5];      // sorted row windows of the first rows of the last two steps (by step parity)
+  int Rp[2][5];         // sorted row windows of the previous step's second row
+  int Pp[2][10];        // the previous step's pair merge
+  int mk[2][2];         // medians of the previous step's rows: the output mask
+  double hs[8][2];      // Gaussian horizontal sums of median rows, slot (row - q0) & 7
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Fw[0][c][k] = Fw[1][c][k] = Rp[c][k] = 0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) Pp[c][k] = 0;
+    mk[0][c] = mk[1][c] = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) hs[k][0] = hs[k][1] = 0.0;
+
+  // rows of the stage-4 map (border rows replicated), the extension applied,
+  // fetched two steps ahead of their use
+  int pa[4], pb[4];
+  auto fetch = [&](int r, int slot) {
+    const unsigned rowoff = (unsigned)clampi_s(q0 + r, 0, H - 1) * W4;
+    pa[slot] = ldk(v4, max(rowoff + oxa, toffa));
+    pb[slot] = ldk(v4, max(rowoff + oxb, toffb));
+  };
+#pragma unroll
+  for (int u = 0; u < 4; ++u) fetch(u, u);
+
+  auto hsum = [&](int ma, int mb, double& ha, double& hb) __attribute__((always_inline)) {
+    // binomial taps (1 4 6 4 1) as integers: exact in float64
+    const int La = from_prev(ma), Lb = from_prev(mb), Ra = from_next(ma), Rb = from_next(mb);
+    ha = hsum5(6.0, 4.0, 1.0, La, Lb, ma, mb, Ra);
+    hb = hsum5(6.0, 4.0, 1.0, Lb, ma, mb, Ra, Rb);
+  };
+  auto vsum = [&](double m2, double m1, double c, double p1, double p2) __attribute__((always_inline)) {
+    return fma(6.0, c, fma(4.0, m1 + p1, m2 + p2));
+  };
+
+  // Step s (slot u = s mod 4; WARM: the first four steps, which give no
+  // output row): r = 2s is the step's first input row relative to q0.
+  auto step = [&](auto u_tag, const int r, auto warm_tag) __attribute__((always_inline)) {
+    constexpr int u = decltype(u_tag)::value;
+    constexpr bool WARM = decltype(warm_tag)::value;
+    constexpr int s0 = (2 * u) & 3, s1 = (2 * u + 1) & 3;
+    const int q = q0 + r;
+    // cells the fill ahead of this pass completed carry kFillTag
+    const int a0 = detach(pa[s0]) & ~kFillTag, b0 = detach(pb[s0]) & ~kFillTag;
+    const int a1 = detach(pa[s1]) & ~kFillTag, b1 = detach(pb[s1]) & ~kFillTag;
+    fetch(r + 4, s0);
+    fetch(r + 5, s1);
+    // sorted 5-wide row windows of rows q and q + 1 at the lane's columns
+    int W0[2][5], W1[2][5];
+    {
+      const int c0[6] = {from_prev(a0), from_prev(b0), a0, b0, from_next(a0), from_next(b0)};
+      const int c1[6] = {from_prev(a1), from_prev(b1), a1, b1, from_next(a1), from_next(b1)};
+      mr::row_windows(c0, W0[0], W0[1]);
+      mr::row_windows(c1, W1[0], W1[1]);
+    }
+    if (!(WARM && u == 0)) {
+      int Pn[2][10];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) net::merge5_5(Rp[c], W0[c], Pn[c]);   // rows q - 1, q
+      if (!(WARM && u == 1)) {
+        // Stage 7: medians of rows q - 2 and q - 1
+        int m0[2], m1[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          int K[6];
+          net::ranks7_12_of_10_10(Pp[c], Pn[c], K);            // rows q - 3 .. q
+          m0[c] = mr::median_of_core(K, Fw[u & 1][c]);          // + row q - 4
+          m1[c] = mr::median_of_core(K, W1[c]);                 // + row q + 1
+        }
+        // Stage 8: horizontal sums of the two median rows (out-of-image
+        // columns take their reflect-101 column's median)
+        int e0a = m0[0], e0b = m0[1], e1a = m1[0], e1b = m1[1];
+        if (edge_cols) {
+          const int f0a = __shfl(e0a, sla), f0b = __shfl(e0b, sla), g0a = __shfl(e0a, slb), g0b = __shfl(e0b, slb);
+          const int f1a = __shfl(e1a, sla), f1b = __shfl(e1b, sla), g1a = __shfl(e1a, slb), g1b = __shfl(e1b, slb);
+          if (!ina) { e0a = sela ? f0b : f0a; e1a = sela ? f1b : f1a; }
+          if (!inb) { e0b = selb ? g0b : g0a; e1b = selb ? g1b : g1a; }
+        }
+        hsum(e0a, e0b, hs[(u * 2 + 6) & 7][0], hs[(u * 2 + 6) & 7][1]);   // row q - 2: slot r - 2
+        hsum(e1a, e1b, hs[(u * 2 + 7) & 7][0], hs[(u * 2 + 7) & 7][1]);   // row q - 1: slot r - 1
+        if (!INTERIOR) {
+          // reflected rows: H mirrors H - 2, H + 1 mirrors H - 3
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int m = q - 2 + k;
+            double* h = hs[(u * 2 + 6 + k) & 7];
+            if (m == H) { h[0] = hs[(u * 2 + 4 + k) & 7][0]; h[1] = hs[(u * 2 + 4 + k) & 7][1]; }
+            else if (m == H + 1) { h[0] = hs[(u * 2 + 2 + k) & 7][0]; h[1] = hs[(u * 2 + 2 + k) & 7][1]; }
+          }
+          // rows -2 and -1 mirror rows 2 and 1 (ready once rows 2 and 3 are in)
+          if (ty0 == 0 && q == 4) {
+            hs[(u * 2 + 2) & 7][0] = hs[(u * 2 + 6) & 7][0];
+            hs[(u * 2 + 2) & 7][1] = hs[(u * 2 + 6) & 7][1];
+            hs[(u * 2 + 3) & 7][0] = hs[(u * 2 + 5) & 7][0];
+            hs[(u * 2 + 3) & 7][1] = hs[(u * 2 + 5) & 7][1];
+          }
+        }
+        if (!WARM) {
+          // Stages 8 and 9 for rows q - 4 and q - 3: the vertical sums, the
+          // mask of the median rows, the output inversion
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int g = q - 4 + k;
+            if (INTERIOR || g < H) {
+              const int sl = u * 2 + 4 + k;      // slot of row g
+              const double ga = vsum(hs[(sl - 2) & 7][0], hs[(sl - 1) & 7][0], hs[sl & 7][0], hs[(sl + 1) & 7][0],
+                                     hs[(sl + 2) & 7][0]);
+              const double gb = vsum(hs[(sl - 2) & 7][1], hs[(sl - 1) & 7][1], hs[sl & 7][1], hs[(sl + 1) & 7][1],
+                                     hs[(sl + 2) & 7][1]);
+              const bool ma = mk[k][0] > kthr, mb = mk[k][1] > kthr;
+              const float oa = ma ? off - (float)(ga * (1.0 / 256.0)) : 0.f;
+              const float ob = mb ? off - (float)(gb * (1.0 / 256.0)) : 0.f;
+              const unsigned ro = (unsigned)g * W4;
+              if (outa) stk(out, ro + ua, key(oa));
+              if (outb) stk(out, ro + ub, key(ob));
+            }
+          }
+        }
+        mk[0][0] = m0[0];
+        mk[0][1] = m0[1];
+        mk[1][0] = m1[0];
+        mk[1][1] = m1[1];
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Pp[c][k] = Pn[c][k];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        Fw[u & 1][c][k] = W0[c][k];
+        Rp[c][k] = W1[c][k];
+      }
+  };
+
+  // four steps (eight rows) per block; the first block only fills the
+  // windows, the ring and the mask (TH / 2 + 4 steps in all)
+  auto block = [&](const int rb, auto warm_tag) __attribute__((always_inline)) {
+    step(std::integral_constant<int, 0>{}, rb, warm_tag);
+    step(std::integral_constant<int, 1>{}, rb + 2, warm_tag);
+    step(std::integral_constant<int, 2>{}, rb + 4, warm_tag);
+    step(std::integral_constant<int, 3>{}, rb + 6, warm_tag);
+  };
+  block(0, std::true_type{});
+  for (int rb = 8; rb < TH + 8; rb += 8) block(rb, std::false_type{});
+}
+
+// Phase 2 of chains other than the default one (the stage hooks 5-9 among
+// them): one TH x 120 tile per wave and pass.
+template <int TH>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) void k_global_stream(FrameSource src, KParams kp) {
   __shared__ int s_cells[4 * kCellEmpty];
   const int lane = threadIdx.x;
@@ -764,12 +964,37 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int gt = t - f.gtile0;
     const int tr = gt / f.gcols;
     const int ty0 = tr * TH, tx0 = (gt - tr * f.gcols) * kGlobalTW;
-    // FAST tiles whose rows all lie away from the frame's first and last two
-    // rows take a variant without the Gaussian's border rows
-    if (FAST && ty0 >= 4 && ty0 + TH + 2 <= f.H)
-      global_stream_tile<TH, false, FAST, FAST>(f, kp, t, fidx, gt, ty0, tx0, lane, slow, cap, s_cells);
-    else
-      global_stream_tile<TH, false, FAST, false>(f, kp, t, fidx, gt, ty0, tx0, lane, slow, cap, s_cells);
+    global_stream_tile<TH, false>(f, kp, t, fidx, gt, ty0, tx0, lane, slow, cap, s_cells);
+  }
+}
+
+// Phase 2 of the default chain (rows_first_tile): tiles whose rows all lie
+// away from the frame's first and last two rows take the variant without the
+// Gaussian's reflected rows.  Frames under 3 rows or columns go to the LDS
+// kernel.  Up to 168 registers (three waves per SIMD): the row windows,
+// the pair merge and the ring of sums stay in registers.
+template <int TH>
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) void k_global_rows(FrameSource src, KParams kp) {
+  const int lane = threadIdx.x;
+  const int total = src.plan ? src.plan->gtiles : src.single_gtiles;
+  int32_t* slow = src.plan ? src.plan->slow : src.slow;
+  const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
+  for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+    FrameDesc f = src.plan ? plan_frame(src, gc(src.plan->gtab)[t]) : src.single;
+    f = uniform_frame(f);
+    const int gt = t - f.gtile0;
+    const int tr = gt / f.gcols;
+    const int ty0 = tr * TH, tx0 = (gt - tr * f.gcols) * kGlobalTW;
+    if (f.H < 3 || f.W < 3) {
+      if (lane == 0) {
+        const int pos = atomic_add_g(slow + 1, 1);
+        if (pos < cap) gw(slow)[lds_queue_offset(cap) + pos] = t;
+      }
+    } else if (ty0 >= 4 && ty0 + TH + 2 <= f.H) {
+      rows_first_tile<TH, true>(f, kp, ty0, tx0, lane);
+    } else {
+      rows_first_tile<TH, false>(f, kp, ty0, tx0, lane);
+    }
   }
 }
 
@@ -1261,7 +1486,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
 
 // Phase 2, queued quarters, step 2: median, blur and output inversion of
 // the quarter again, with the stage-6 values of step 1.
-template <int TH, bool FAST>
+template <int TH>
 __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) void k_global_patched(FrameSource src, KParams kp) {
   constexpr int QR = TH / 4;
   const int lane = threadIdx.x;
@@ -1277,7 +1502,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) voi
     FrameDesc f = src.plan ? plan_frame(src, fidx) : src.single;
     f = uniform_frame(f);
     const int tr = gt / f.gcols;
-    global_stream_tile<QR, true, FAST>(f, kp, 0, fidx, gt, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane,
+    global_stream_tile<QR, true>(f, kp, 0, fidx, gt, tr * TH + qk * QR, (gt - tr * f.gcols) * kGlobalTW, lane,
                                        nullptr, 0, nullptr);
   }
 }
@@ -1331,16 +1556,16 @@ hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int ti
 
 hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, bool fast, int grid,
                                 hipStream_t s) {
-#define IPB_GS(TH)                                                                                     \
-  if (fast) hipLaunchKernelGGL((k_global_stream<TH, true>), dim3(grid), dim3(kLanes), 0, s, src, kp); \
-  else hipLaunchKernelGGL((k_global_stream<TH, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+#define IPB_GS(TH)                                                                           \
+  if (fast) hipLaunchKernelGGL((k_global_rows<TH>), dim3(grid), dim3(kLanes), 0, s, src, kp); \
+  else hipLaunchKernelGGL((k_global_stream<TH>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   if (tile_id == 5) { IPB_GS(64) }
   else if (tile_id == 6) { IPB_GS(32) }
   else if (tile_id == 7) { IPB_GS(128) }
   else if (tile_id == 8 && fast)   // 16- and 8-row tiles: the default chain only
-    hipLaunchKernelGGL((k_global_stream<16, true>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+    hipLaunchKernelGGL((k_global_rows<16>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else if (tile_id == 9 && fast)
-    hipLaunchKernelGGL((k_global_stream<8, true>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+    hipLaunchKernelGGL((k_global_rows<8>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   else return hipErrorInvalidValue;
 #undef IPB_GS
   return hipGetLastError();
@@ -1362,9 +1587,9 @@ hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int t
   else return hipErrorInvalidValue;
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (tile_id == 5) hipLaunchKernelGGL((k_global_patched<64, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else if (tile_id == 6) hipLaunchKernelGGL((k_global_patched<32, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
-  else hipLaunchKernelGGL((k_global_patched<128, false>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  if (tile_id == 5) hipLaunchKernelGGL((k_global_patched<64>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else if (tile_id == 6) hipLaunchKernelGGL((k_global_patched<32>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+  else hipLaunchKernelGGL((k_global_patched<128>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   return hipGetLastError();
 }
 
@@ -1384,7 +1609,7 @@ int prefill_resident_blocks() {
 }
 
 // The default chain (5x5 median, the binomial 5x5 Gaussian, every stage, the
-// full extension): the phase-2 kernel's FAST variant.  The host takes it only
+// full extension): phase 2 then runs k_global_rows.  The host takes it only
 // with the streaming phase 1, whose column records the fill ahead of phase 2
 // reads.
 bool fast_chain(const KParams& kp) {
@@ -1400,11 +1625,11 @@ int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast)
 #undef X
     return 1;
   }
-  if (tile_id == 5) return fast ? occupancy_s(k_global_stream<64, true>) : occupancy_s(k_global_stream<64, false>);
-  if (tile_id == 6) return fast ? occupancy_s(k_global_stream<32, true>) : occupancy_s(k_global_stream<32, false>);
-  if (tile_id == 7) return fast ? occupancy_s(k_global_stream<128, true>) : occupancy_s(k_global_stream<128, false>);
-  if (tile_id == 8 && fast) return occupancy_s(k_global_stream<16, true>);
-  if (tile_id == 9 && fast) return occupancy_s(k_global_stream<8, true>);
+  if (tile_id == 5) return fast ? occupancy_s(k_global_rows<64>) : occupancy_s(k_global_stream<64>);
+  if (tile_id == 6) return fast ? occupancy_s(k_global_rows<32>) : occupancy_s(k_global_stream<32>);
+  if (tile_id == 7) return fast ? occupancy_s(k_global_rows<128>) : occupancy_s(k_global_stream<128>);
+  if (tile_id == 8 && fast) return occupancy_s(k_global_rows<16>);
+  if (tile_id == 9 && fast) return occupancy_s(k_global_rows<8>);
   return 1;
 }
 

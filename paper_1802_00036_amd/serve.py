@@ -31,11 +31,14 @@ kept for reuse); when nothing runs and the next request does not fit, the
 executor is asked to drop idle resident memory first.
 
 Stream order: a request's frame may come from work on another stream.  The
-GPU executors record an event on the submitting thread's current stream when
-the request is submitted (or take the client's own event), and the slot
-stream waits for it before the launch reads the frame; an output buffer
-that returns to the pool is reused only after an event recorded on the
-releasing thread's current stream.
+GPU executors note the submitting thread's current stream when a request is
+submitted (or take the client's own event); before a launch reads the
+frames, the slot stream waits for an event recorded on each such stream (one
+per distinct stream of the batch), which covers all work the client queued
+there before submitting.  An output buffer the client releases is reused
+only after an event recorded on the releasing thread's current stream; one
+the server releases itself (outputs not kept) needs none, as the batch that
+wrote it has completed and nothing else read it.
 
 Every frame is completed independently of the others in its batch (Sec. II),
 so a result does not depend on what it was batched with.
@@ -86,6 +89,7 @@ class Request:
     t_done: float = math.nan
     deadline: float = math.inf         # launch by then, or the request times out
     ready: object = None               # event after the work that produced `frame` (GPU executors)
+    src: object = None                 # stream current when submitted (GPU executors)
     attempts: int = 0                  # launches that failed
     solo: bool = False                 # to be launched alone (a retry after a failed batch)
     cancelled: bool = False            # cancelled while running: released when it completes
@@ -116,8 +120,10 @@ class Executor:
     def outputs(self, handle: object) -> List[object]:
         raise NotImplementedError
 
-    def recycle(self, outs: Sequence[object]) -> None:
-        """Output buffers the client has finished with."""
+    def recycle(self, outs: Sequence[object], by_client: bool = True) -> None:
+        """Output buffers handed back: by the client (who may still have
+        reads of them queued on its current stream), or by the server itself
+        right after their batch completed."""
 
     def resident_bytes(self) -> int:
         """Device memory the executor keeps between batches."""
@@ -229,7 +235,7 @@ class Server:
             done.append(r)
             if not self.keep_outputs:
                 back.append(r)
-        self.release_many(back)
+        self.release_many(back, by_client=False)
         for r in back:
             if r.cancelled:
                 r.status = "cancelled"
@@ -380,7 +386,7 @@ class Server:
         current stream, such as the client's reads of it, is done)."""
         self.release_many([req])
 
-    def release_many(self, reqs: Sequence[Request]) -> None:
+    def release_many(self, reqs: Sequence[Request], by_client: bool = True) -> None:
         outs = []
         for req in reqs:
             if req.status != "done" or req.out is None:
@@ -390,7 +396,7 @@ class Server:
             req.status = "released"
             self.in_use -= req.nbytes
         if outs:
-            self.ex.recycle(outs)
+            self.ex.recycle(outs, by_client)
 
     # ------------------------------------------------------------- statistics --
     def stats(self, since: float = 0.0) -> dict:
@@ -482,11 +488,17 @@ class BufferPool:
         with torch.cuda.stream(stream):
             return torch.empty(shape, dtype=torch.float32, device=self.device)
 
-    def put(self, bufs: Sequence[object]) -> None:
+    def put(self, bufs: Sequence[object], by_client: bool = True) -> None:
+        """Buffers back to the pool.  by_client: the releasing thread may
+        still have reads of them queued on its current stream, so their next
+        writer waits for an event recorded there; otherwise (the server
+        releases outputs no client saw) their last use has completed."""
         if not bufs:
             return
-        ev = torch.cuda.Event()
-        ev.record(torch.cuda.current_stream(self.device))
+        ev = None
+        if by_client:
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(self.device))
         for b in bufs:
             self.free[tuple(b.shape)].append((b, ev))
             self.free_bytes += 4 * b.numel()
@@ -496,22 +508,39 @@ class BufferPool:
         self.free_bytes = 0
 
 
-def _wait_inputs(stream, reqs: Sequence[Request]) -> None:
-    """Order `stream` after the work that produced the requests' frames."""
-    seen = set()
-    for r in reqs:
-        if r.ready is not None and id(r.ready) not in seen:
-            seen.add(id(r.ready))
-            stream.wait_event(r.ready)
+class _InputOrder:
+    """Orders a launch stream after the work that produced its frames: the
+    client's events, and, for requests without one, an event recorded now on
+    each stream that was current at their submission (once per distinct
+    stream; an event recorded later than the submission covers the client's
+    work queued before it).  One event object is reused: a stream's wait
+    takes the event's state at the time of the call."""
+
+    def __init__(self):
+        self.ev = torch.cuda.Event()
+
+    def wait(self, stream, reqs: Sequence[Request]) -> None:
+        seen = set()
+        for r in reqs:
+            if r.ready is not None:
+                if id(r.ready) not in seen:
+                    seen.add(id(r.ready))
+                    stream.wait_event(r.ready)
+            elif r.src is not None:
+                h = r.src.cuda_stream
+                if h not in seen and h != stream.cuda_stream:
+                    seen.add(h)
+                    self.ev.record(r.src)
+                    stream.wait_event(self.ev)
 
 
-def _note_submit(req: Request, device) -> None:
-    """Record, when the client gave no event, one on the current stream: the
-    frame is ready once the work queued there so far is done."""
-    if req.ready is None:
-        ev = torch.cuda.Event()
-        ev.record(torch.cuda.current_stream(device))
-        req.ready = ev
+def _note_submit(req: Request, device, order_inputs: bool) -> None:
+    """Note the submitting thread's current stream (the client's event, if it
+    gave one, takes precedence).  order_inputs False: the client guarantees
+    its frames are complete when submitted (e.g. resident frames made before
+    a synchronisation), so nothing is noted."""
+    if req.ready is None and order_inputs:
+        req.src = torch.cuda.current_stream(device)
 
 
 class GraphExecutor(Executor):
@@ -521,12 +550,16 @@ class GraphExecutor(Executor):
     tier that holds it, so a lone request under light load does not pay for
     the launch grid of a full batch.  With `direct_single`, a lone request
     skips the graph (and its plan copy) and goes straight to ipb_complete_ws
-    on the slot's stream, with a workspace resident per slot."""
+    on the slot's stream, with a workspace resident per slot.  order_inputs:
+    launches wait for the streams the frames were submitted on (see the
+    module notes); False for clients whose frames are complete when
+    submitted."""
 
     def __init__(self, slots: int = 2, max_batch: int = 16, device=None, default_params=None,
-                 tiers: Optional[Sequence[int]] = None, direct_single: bool = True):
+                 tiers: Optional[Sequence[int]] = None, direct_single: bool = True, order_inputs: bool = True):
         from .api import Params
         self.direct_single = direct_single
+        self.order_inputs = order_inputs
         self.ws: Dict[int, object] = {}
         self.ws_bytes: Dict[int, int] = {}
         self.cparams: Dict[Hashable, object] = {}
@@ -543,6 +576,9 @@ class GraphExecutor(Executor):
         # engines by (slot, bucket, tier), least recently used first
         self.engines: "collections.OrderedDict[Tuple[int, Hashable, int], object]" = collections.OrderedDict()
         self.pool = BufferPool(self.device)
+        self.order = _InputOrder()
+        self._eng_bytes = 0        # workspaces and plans of the engines
+        self._ws_total = 0         # the per-slot workspaces of lone requests
 
     def _engine(self, slot: int, bucket: Hashable, params, n: int):
         from .batch import GraphBatch
@@ -554,18 +590,18 @@ class GraphExecutor(Executor):
             eng = GraphBatch([(Hb, Wb)] * tier, params or self.default_params, device=self.device,
                              stream=self.streams[slot])
             self.engines[key] = eng
+            self._eng_bytes += eng.ws_bytes + eng.plan_bytes
         else:
             self.engines.move_to_end(key)
         return eng
 
     def submitted(self, req: Request) -> None:
-        _note_submit(req, self.device)
+        _note_submit(req, self.device, self.order_inputs)
 
     def resident_bytes(self) -> int:
         """Engine workspaces and plans, the per-slot workspaces of lone
         requests and the released output buffers kept for reuse."""
-        eng = sum(e.ws_bytes + e.plan_bytes for e in self.engines.values())
-        return eng + sum(self.ws_bytes.values()) + self.pool.free_bytes
+        return self._eng_bytes + self._ws_total + self.pool.free_bytes
 
     def trim(self, target: int) -> None:
         """Drop pooled outputs, then least recently used engines and the
@@ -573,10 +609,12 @@ class GraphExecutor(Executor):
         called while nothing runs, so nothing dropped is in use)."""
         self.pool.clear()
         while self.engines and self.resident_bytes() > target:
-            self.engines.popitem(last=False)
+            _, e = self.engines.popitem(last=False)
+            self._eng_bytes -= e.ws_bytes + e.plan_bytes
         if self.resident_bytes() > target:
             self.ws.clear()
             self.ws_bytes.clear()
+            self._ws_total = 0
 
     def warm(self, bucket_params: Sequence[Tuple[Hashable, object]]) -> None:
         """Capture the graphs of these buckets on every slot and tier ahead
@@ -606,9 +644,10 @@ class GraphExecutor(Executor):
         if need > self.ws_bytes.get(slot, 0):
             with torch.cuda.stream(stream):
                 self.ws[slot] = _workspace(need, self.device)
+            self._ws_total += need - self.ws_bytes.get(slot, 0)
             self.ws_bytes[slot] = need
         o = self.pool.get(r.shape, stream)
-        _wait_inputs(stream, [r])
+        self.order.wait(stream, [r])
         L.check(lib.ipb_complete_ws(ctypes.c_void_p(r.frame.data_ptr()), H, W, ctypes.byref(cp),
                                     ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(self.ws[slot].data_ptr()),
                                     self.ws_bytes[slot], ctypes.c_void_p(stream.cuda_stream)), "ipb_complete_ws")
@@ -621,7 +660,7 @@ class GraphExecutor(Executor):
             return self._direct(slot, reqs[0])
         eng = self._engine(slot, bucket, reqs[0].params, len(reqs))
         outs = [self.pool.get(r.shape, eng.stream) for r in reqs]
-        _wait_inputs(eng.stream, reqs)
+        self.order.wait(eng.stream, reqs)
         ev = eng.run([r.frame for r in reqs], outs)
         return ev, outs
 
@@ -631,21 +670,22 @@ class GraphExecutor(Executor):
     def outputs(self, handle) -> List[object]:
         return handle[1]
 
-    def recycle(self, outs: Sequence[object]) -> None:
-        self.pool.put(outs)
+    def recycle(self, outs: Sequence[object], by_client: bool = True) -> None:
+        self.pool.put(outs, by_client)
 
 
 class PerFrameExecutor(Executor):
     """The plain path: every request is one ipb_complete_ws call on a single
     stream as soon as it is admitted, so the device runs them in arrival
     order (one resident workspace serves them all).  `slots` bounds the
-    requests in flight."""
+    requests in flight; order_inputs as for GraphExecutor."""
 
     in_order = True
 
-    def __init__(self, slots: int = 4096, device=None, default_params=None):
+    def __init__(self, slots: int = 4096, device=None, default_params=None, order_inputs: bool = True):
         from .api import Params
         self.slots = slots
+        self.order_inputs = order_inputs
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.default_params = default_params or Params()
         self.stream = torch.cuda.Stream(device=self.device)
@@ -653,6 +693,7 @@ class PerFrameExecutor(Executor):
         self.ws_bytes = 0
         self.cparams: Dict[Hashable, object] = {}
         self.pool = BufferPool(self.device)
+        self.order = _InputOrder()
 
     def launch(self, slot: int, bucket: Hashable, reqs: Sequence[Request]):
         import ctypes
@@ -673,7 +714,7 @@ class PerFrameExecutor(Executor):
                     self.ws = _workspace(need, self.device)
                 self.ws_bytes = need
             o = self.pool.get(r.shape, self.stream)
-            _wait_inputs(self.stream, [r])
+            self.order.wait(self.stream, [r])
             L.check(lib.ipb_complete_ws(ctypes.c_void_p(r.frame.data_ptr()), H, W, ctypes.byref(cp),
                                         ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
                                         self.ws_bytes, h), "ipb_complete_ws")
@@ -683,7 +724,7 @@ class PerFrameExecutor(Executor):
         return ev, outs
 
     def submitted(self, req: Request) -> None:
-        _note_submit(req, self.device)
+        _note_submit(req, self.device, self.order_inputs)
 
     def resident_bytes(self) -> int:
         return self.ws_bytes + self.pool.free_bytes
@@ -699,5 +740,5 @@ class PerFrameExecutor(Executor):
     def outputs(self, handle) -> List[object]:
         return handle[1]
 
-    def recycle(self, outs: Sequence[object]) -> None:
-        self.pool.put(outs)
+    def recycle(self, outs: Sequence[object], by_client: bool = True) -> None:
+        self.pool.put(outs, by_client)

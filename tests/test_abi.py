@@ -249,6 +249,53 @@ int main() {
         assert subprocess.run([exe]).returncode == 0
 
 
+def test_row_first_median_on_host():
+    """The blocks of the streaming 5x5 median (median_rows.hpp with the
+    generated merges of networks.hpp), composed as the phase-2 kernel
+    composes them, compiled for the CPU: on random 6 x 6 patches (few
+    distinct values, so many ties) the two windows of each of two
+    neighbouring columns and two consecutive rows give the middle of the 25
+    sorted samples."""
+    src = r"""
+#include <cstdio>
+#include <cstdlib>
+#include <algorithm>
+#include "networks.hpp"
+#include "median_rows.hpp"
+int main() {
+  srand(7);
+  for (int it = 0; it < 200000; ++it) {
+    int v[6][6];
+    const int range = it % 3 == 0 ? 3 : (it % 3 == 1 ? 40 : 1 << 20);
+    for (int y = 0; y < 6; ++y) for (int x = 0; x < 6; ++x) v[y][x] = rand() % range;
+    int R[6][2][5];
+    for (int y = 0; y < 6; ++y) ipb::mr::row_windows(v[y], R[y][0], R[y][1]);
+    for (int c = 0; c < 2; ++c) {
+      int P1[10], P2[10], K[6];
+      ipb::net::merge5_5(R[1][c], R[2][c], P1);
+      ipb::net::merge5_5(R[3][c], R[4][c], P2);
+      ipb::net::ranks7_12_of_10_10(P1, P2, K);
+      for (int o = 0; o < 2; ++o) {
+        const int got = ipb::mr::median_of_core(K, R[o == 0 ? 0 : 5][c]);
+        int w[25], n = 0;
+        for (int y = o; y < o + 5; ++y) for (int x = c; x < c + 5; ++x) w[n++] = v[y][x];
+        std::nth_element(w, w + 12, w + 25);
+        if (got != w[12]) { printf("it %d col %d row %d: %d != %d\n", it, c, o, got, w[12]); return 1; }
+      }
+    }
+  }
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        cpp = os.path.join(d, "t.cpp")
+        exe = os.path.join(d, "t")
+        with open(cpp, "w") as fh:
+            fh.write(src)
+        subprocess.run(["g++", "-O2", "-std=c++17", f"-I{CSRC}", cpp, "-o", exe], check=True)
+        assert subprocess.run([exe]).returncode == 0
+
+
 def test_median_network_on_host():
     """The sorting network the median kernel uses, compiled for the CPU:
     sorts, and its middle output is the median, for every window size used."""

@@ -47,7 +47,7 @@ class FakeExecutor(serve.Executor):
     def outputs(self, h):
         return h["outs"]
 
-    def recycle(self, outs):
+    def recycle(self, outs, by_client=True):
         self.recycled = getattr(self, "recycled", 0) + len(outs)
 
 
