@@ -747,6 +747,17 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
 // and H, H + 1) are copies of its sums of rows 1, 2 and H - 2, H - 3, and
 // its reflected columns come from the lanes that hold them.  INTERIOR tiles
 // need none of these rows.
+//
+// Rows above the extension's reach: in a column with a top, every stage-5
+// row at or above the top holds the top cell's value (Sec. III "Extension
+// to Top of Frame"), and the fill leaves such non-empty cells alone.  An
+// output row g whose median and blur windows (rows g - 4 .. g + 4) lie at or
+// above the top of every column the wave reads therefore sees five equal
+// rows: its median is the middle of the row's sorted 5-window, its blur is
+// 16 times the row's horizontal sum, and every such row of the tile has the
+// same outputs.  They are computed once from the top cells and stored to
+// those rows; the streaming loop runs over the remaining rows (a multiple
+// of 8, from the tile's end) only.
 template <int TH, bool INTERIOR>
 __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParams& kp, int ty0, int tx0, int lane) {
   static_assert(TH % 8 == 0, "tile rows");
@@ -768,12 +779,20 @@ __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParam
   // V5[y][x] = V4[max(y, top)][x]; as byte offsets, the larger of the row's
   // and the top cell's (0 without a top or without the extension).
   unsigned toffa = 0, toffb = 0;
+  int sky = 0;                          // rows from 0 whose outputs are the sky row's (see above)
   if (kp.extrapolate) {
     gcint* top = gc(f.top);
     const int t_a = top[xa], t_b = top[xb];
     if (t_a < H) toffa = (unsigned)t_a * W4 + oxa;
     if (t_b < H) toffb = (unsigned)t_b * W4 + oxb;
+    // the least top over the wave's columns (0 if a column has none)
+    const int mine = (t_a < H && t_b < H) ? min(t_a, t_b) : 0;
+    sky = 0x7fffffff - wave_max_nonneg(0x7fffffff - mine) - 3;   // rows g < least top - 3
   }
+  // output rows ty0 .. r_start - 1 are sky rows; the loop covers r_start ..
+  // ty0 + TH - 1, a multiple of 8 rows
+  int r_start = ty0;
+  if (sky > ty0) r_start = ty0 + TH - 8 * ((ty0 + TH - min(sky, ty0 + TH) + 7) / 8);
   // reflect-101 source lane/slot of this lane's columns, for the Gaussian's border
   int sla = 0, slb = 0;
   bool sela = false, selb = false;
@@ -789,7 +808,32 @@ __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParam
     sela = (sa & 1) != 0;
     selb = (sb & 1) != 0;
   }
-  const int q0 = ty0 - 4;              // first input row; step s takes rows q0 + 2s, q0 + 2s + 1
+  if (r_start > ty0) {
+    // the sky row: the top cells' values, their row medians and blur
+    const int a0 = ldk(v4, toffa) & ~kFillTag, b0 = ldk(v4, toffb) & ~kFillTag;
+    const int c0[6] = {from_prev(a0), from_prev(b0), a0, b0, from_next(a0), from_next(b0)};
+    int Wa[5], Wb[5];
+    mr::row_windows(c0, Wa, Wb);
+    int ea = Wa[2], eb = Wb[2];                    // medians of five equal rows
+    const bool ma = ea > kthr, mb = eb > kthr;     // (masks of the in-image columns)
+    if (edge_cols) {
+      const int fa = __shfl(ea, sla), fb = __shfl(eb, sla), ga = __shfl(ea, slb), gb = __shfl(eb, slb);
+      if (!ina) ea = sela ? fb : fa;
+      if (!inb) eb = selb ? gb : ga;
+    }
+    const int La = from_prev(ea), Lb = from_prev(eb), Ra = from_next(ea), Rb = from_next(eb);
+    const double ha = hsum5(6.0, 4.0, 1.0, La, Lb, ea, eb, Ra), hb = hsum5(6.0, 4.0, 1.0, Lb, ea, eb, Ra, Rb);
+    // the vertical taps sum to 16: (16 h) / 256 = h / 16, exactly
+    const int oa = key(ma ? off - (float)(ha * (1.0 / 16.0)) : 0.f);
+    const int ob = key(mb ? off - (float)(hb * (1.0 / 16.0)) : 0.f);
+    for (int g = ty0; g < r_start; ++g) {
+      const unsigned ro = (unsigned)g * W4;
+      if (outa) stk(out, ro + ua, oa);
+      if (outb) stk(out, ro + ub, ob);
+    }
+    if (r_start == ty0 + TH) return;
+  }
+  const int q0 = r_start - 4;           // first input row; step s takes rows q0 + 2s, q0 + 2s + 1
 
   int Fw[2][2][5];      // sorted row windows of the first rows of the last two steps (by step parity)
   int Rp[2][5];         // sorted row windows of the previous step's second row
@@ -883,7 +927,7 @@ __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParam
             else if (m == H + 1) { h[0] = hs[(u * 2 + 2 + k) & 7][0]; h[1] = hs[(u * 2 + 2 + k) & 7][1]; }
           }
           // rows -2 and -1 mirror rows 2 and 1 (ready once rows 2 and 3 are in)
-          if (ty0 == 0 && q == 4) {
+          if (r_start == 0 && q == 4) {
             hs[(u * 2 + 2) & 7][0] = hs[(u * 2 + 6) & 7][0];
             hs[(u * 2 + 2) & 7][1] = hs[(u * 2 + 6) & 7][1];
             hs[(u * 2 + 3) & 7][0] = hs[(u * 2 + 5) & 7][0];
@@ -939,7 +983,7 @@ __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParam
     step(std::integral_constant<int, 3>{}, rb + 6, warm_tag);
   };
   block(0, std::true_type{});
-  for (int rb = 8; rb < TH + 8; rb += 8) block(rb, std::false_type{});
+  for (int rb = 8; rb < ty0 + TH - r_start + 8; rb += 8) block(rb, std::false_type{});
 }
 
 // Phase 2 of chains other than the default one (the stage hooks 5-9 among

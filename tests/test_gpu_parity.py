@@ -317,3 +317,36 @@ def test_batch_uniform_workload_sample():
     outs = api.complete_batch(ts)
     for f, o in zip(frames, outs):
         assert_stage_equal(o.cpu().numpy(), oracle.complete_map(f.sparse), "batch c2")
+
+
+# ------------------------------------------- rows above every column's top --
+
+def _sky_frame(H, W, first_row, seed, empty_col=None):
+    """Valid depths only at and below `first_row` (every column gets one
+    there, so every column has a top); optionally one column left empty."""
+    rng = np.random.default_rng(seed)
+    m = np.zeros((H, W), np.float32)
+    below = rng.random((H - first_row, W)) < 0.06
+    m[first_row:][below] = rng.uniform(2.0, 80.0, int(below.sum())).astype(np.float32)
+    cols = np.arange(W)
+    m[first_row + rng.integers(0, 4, W), cols] = rng.uniform(2.0, 80.0, W).astype(np.float32)
+    if empty_col is not None:
+        m[:, empty_col] = 0.0
+    return m
+
+
+@pytest.mark.parametrize("tg", [5, 6, 7, 8, 9])
+@pytest.mark.parametrize("case", ["deep", "shallow", "empty_column", "mid_tile"])
+def test_rows_above_every_top(case, tg):
+    """Output rows whose median and blur windows lie at or above every
+    column's top see five equal rows; the phase-2 kernel stores them from one
+    computed row and streams the rest.  Bit-exact against the oracle for
+    every phase-2 tile height, with sky ends at, above and inside tiles, and
+    with a column that has no top (no shortcut for its waves)."""
+    H, W, first, empty, seed = {"deep": (300, 500, 170, None, 1), "shallow": (90, 300, 5, None, 2),
+                                "empty_column": (300, 500, 170, 250, 3), "mid_tile": (257, 383, 77, None, 4)}[case]
+    m = _sky_frame(H, W, first, seed=[57, seed], empty_col=empty)
+    p = dataclasses.replace(api.Params(), tile_global=tg)
+    want = oracle.complete_map(m, oracle_params(p))
+    got = gpu_stage(m, 9, p)
+    assert_stage_equal(got, want, f"{case} tile {tg}")
