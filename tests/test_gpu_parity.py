@@ -350,3 +350,39 @@ def test_rows_above_every_top(case, tg):
     want = oracle.complete_map(m, oracle_params(p))
     got = gpu_stage(m, 9, p)
     assert_stage_equal(got, want, f"{case} tile {tg}")
+
+
+@pytest.mark.parametrize("tl", [5, 6, 7, 8, 9])
+@pytest.mark.parametrize("case", ["first_row_0", "first_row_13", "first_row_100", "first_row_170",
+                                  "last_row_only", "garbage_on_top", "all_empty", "full7", "full3"])
+def test_empty_rows_on_top(case, tl):
+    """Phase 1 stores the output rows whose window holds no input value as
+    zeros and starts streaming just above the first value: bit-exact against
+    the oracle for every phase-1 tile height, first values at and between
+    tile boundaries, a frame with values in its last row only, garbage that
+    is not zero (NaN, negatives, depths beyond the offset) above the first
+    valid row, an empty frame, and other dilation radii."""
+    H, W = 300, 460
+    p = dataclasses.replace(api.Params(), tile_local=tl)
+    rng = np.random.default_rng([58, tl, len(case)])
+    if case == "all_empty":
+        m = np.zeros((H, W), np.float32)
+    elif case == "last_row_only":
+        m = np.zeros((H, W), np.float32)
+        m[H - 1, ::3] = rng.uniform(2.0, 80.0, len(range(0, W, 3))).astype(np.float32)
+    else:
+        first = {"first_row_0": 0, "first_row_13": 13, "first_row_100": 100, "first_row_170": 170,
+                 "garbage_on_top": 150, "full7": 121, "full3": 64}[case]
+        m = _sky_frame(H, W, first, seed=[58, first])
+        if case == "garbage_on_top":
+            m[3, 7] = np.nan
+            m[40, 200] = -5.0
+            m[90, 401] = 150.0
+            m[120, 13] = -0.0
+        if case == "full7":
+            p = dataclasses.replace(p, dilate_size=7, dilate_shape=api.SE_FULL)
+        if case == "full3":
+            p = dataclasses.replace(p, dilate_size=3, dilate_shape=api.SE_FULL)
+    want = oracle.complete_map(m, oracle_params(p))
+    got = gpu_stage(m, 9, p)
+    assert_stage_equal(got, want, f"{case} tile {tl}")
