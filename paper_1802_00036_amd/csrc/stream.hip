@@ -1131,7 +1131,7 @@ constexpr int kDenseThreads = 256;
 template <int QR, class Out>
 __device__ __forceinline__ void fill_region(const FrameDesc& f, const KParams& kp, int y0, int nr, int x0, int ncols,
                                             int* S, int* s_top, int tid, Out&& out) {
-  static_assert(QR + 2 * kFillRad <= kDenseThreads / 4, "one row of 128 horizontal maxima per four threads");
+  static_assert(QR + 2 * kFillRad <= kLanes, "one staged row per lane for the horizontal maxima");
   const int H = f.H, W = f.W, rl = kp.rl;
   const int kthr = key(kp.thr);
   gcint* v4 = gc(f.v4);
@@ -1143,29 +1143,40 @@ __device__ __forceinline__ void fill_region(const FrameDesc& f, const KParams& k
   }
   __syncthreads();
   {
-    // the loads of a thread in batches of 13, each batch in flight at once
-    // (staged rows past sr load a clamped cell and are not stored)
-    constexpr int PER = ((QR + 2 * kFillRad) * kDW + kDenseThreads - 1) / kDenseThreads;
-    constexpr int B = 13;
-#pragma unroll 1
-    for (int k0 = 0; k0 < PER; k0 += B) {
-      int vals[B];
+    // Each thread stages whole runs of one column, so the column's clamped x,
+    // its top and whether it lies in the image are worked out once: columns
+    // 0 .. 127 by all threads (two halves of the rows), the remaining
+    // kDW - 128 columns by groups of threads over slices of RB rows.
+    // Rows past sr load a clamped cell and are not stored.
+    constexpr int SRM = QR + 2 * kFillRad;
+    constexpr int RA = (SRM + 1) / 2;
+    constexpr int NB = kDW - 128, GB = kDenseThreads / NB, RB = (SRM + GB - 1) / GB;
+    static_assert(kDenseThreads == 256 && NB > 0 && GB * RB >= SRM, "staging split");
+    const int ext = kp.ext_rows;
+    auto stage = [&](int cc, int r0, auto n_rows) {
+      constexpr int N = decltype(n_rows)::value;
+      const int gx = x0 - rl + cc;
+      const unsigned x4 = 4u * (unsigned)clampi_s(gx, 0, W - 1), W4 = 4u * (unsigned)W;
+      const bool colin = gx >= 0 && gx < W;
+      // stage 5 reads the top row for rows lo .. top - 1 of the column (none
+      // when the column has no top)
+      const int top = s_top[cc];
+      const int lo = top >= H ? H : (ext > 0 ? max(top - ext, 0) : 0);
+      const unsigned span = (unsigned)(min(top, H) - lo);
+      const int yb = y0 - rl + r0;
+      int v[N];
 #pragma unroll
-      for (int k = 0; k < B; ++k) {
-        const int idx = tid + (k0 + k) * kDenseThreads;
-        const int rq = idx / kDW, cc = idx - rq * kDW;
-        const int rr = min(rq, sr - 1);
-        const int x = clampi_s(x0 - rl + cc, 0, W - 1), y = clampi_s(y0 - rl + rr, 0, H - 1);
-        vals[k] = ldk(v4, 4u * ((unsigned)v5_row(y, s_top[cc], H, kp.ext_rows) * (unsigned)W + (unsigned)x));
+      for (int k = 0; k < N; ++k) {
+        const int y = clampi_s(yb + k, 0, H - 1);
+        const int row = (unsigned)(y - lo) < span ? top : y;
+        v[k] = ldk(v4, (unsigned)row * W4 + x4);
       }
 #pragma unroll
-      for (int k = 0; k < B; ++k) {
-        const int idx = tid + (k0 + k) * kDenseThreads;
-        const int rr = idx / kDW, cc = idx - rr * kDW;
-        const int gx = x0 - rl + cc, gy = y0 - rl + rr;
-        if (k0 + k < PER && rr < sr) S[idx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? max(vals[k], 0) : 0;
-      }
-    }
+      for (int k = 0; k < N; ++k)
+        if (r0 + k < sr) S[(r0 + k) * kDW + cc] = (colin && (unsigned)(yb + k) < (unsigned)H) ? max(v[k], 0) : 0;
+    };
+    stage(tid & 127, (tid >> 7) * RA, std::integral_constant<int, RA>{});
+    if (tid < GB * NB) stage(128 + tid % NB, (tid / NB) * RB, std::integral_constant<int, RB>{});
   }
   __syncthreads();
   // the region's cells that are empty after stage 5, one column per thread
@@ -1178,7 +1189,7 @@ __device__ __forceinline__ void fill_region(const FrameDesc& f, const KParams& k
   // horizontal window maxima of 128 (>= ncols) columns, written over the
   // staged values once every row has been read
   {
-    const int rr = tid >> 2, j0 = (tid & 3) * 32;
+    const int rr = tid & (kLanes - 1), j0 = (tid / kLanes) * 32;   // a wave per run: lanes 158 ints apart
     const bool act = rr < sr;
     int o[32];
     if (act) {
