@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import dataclasses
 import hashlib
 import json
 import multiprocessing as mp
@@ -331,7 +332,6 @@ class Batches:
         chosen for whole batches)."""
         torch, api, L = self.torch, self.api, self.L
         st = self.sets[0]
-        import dataclasses
         single = dataclasses.replace(self.params, tile_local=0, tile_global=0)
         cp = single.to_c()
         fws = api._workspace(max(api.workspace_bytes(H, W, single) for H, W in self.shapes), self.dev)
@@ -405,7 +405,11 @@ def bench_batch(args, workload, cpu, serve_host=None):
     # tile shapes tuned for this batch, run as the timed pass runs it (batches
     # in flight on args.streams streams): the user cache's or the shipped
     # table's entry, else tuned here
-    if not args.no_tune:
+    if args.tiles:
+        tl, tg = (int(v) for v in args.tiles.split("/"))
+        params = dataclasses.replace(params, tile_local=tl, tile_global=tg)
+        extra["autotune"] = {"tile_local": tl, "tile_global": tg, "source": "--tiles"}
+    elif not args.no_tune:
         from paper_1802_00036_amd import autotune
         probe = [torch.from_numpy(m).to("cuda:0") for m in maps]
         report = []
@@ -555,6 +559,8 @@ def main() -> None:
     ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated frames per size for serving")
     ap.add_argument("--no-serving", action="store_true", help="c2: skip the serving summary")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes instead of the autotuner's")
+    ap.add_argument("--tiles", default=None, metavar="L/G",
+                    help="batched workloads: phase-1/phase-2 tile ids to run instead of the autotuner's")
     ap.add_argument("--retune", action="store_true",
                     help="tune now instead of taking the cached or shipped entry for the batch")
     ap.add_argument("--copy-probe", action="store_true",

@@ -241,9 +241,11 @@ const char* ipb_status_string(int status);
 int ipb_last_hip_error(void);
 
 /* Tile shapes (rows, cols) of a tile id for phase 1 (local) or 2 (global);
- * returns IPB_ERR_INVALID_ARG for an unknown id.  Id 0 = automatic.  Phase-2
- * ids 8 and 9 (16- and 8-row streaming tiles) serve the default chain only;
- * with any other chain they are IPB_ERR_UNSUPPORTED. */
+ * returns IPB_ERR_INVALID_ARG for an unknown id.  Id 0 = automatic.  Ids
+ * 1-4 are LDS tiles, 5 and up streaming tiles (phase 1: 64, 128, 32, 16, 8
+ * and 96 rows of 108 columns for ids 5-10).  Phase-2 ids 8 and 9 (16- and
+ * 8-row streaming tiles) serve the default chain only; with any other chain
+ * they are IPB_ERR_UNSUPPORTED. */
 int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols);
 
 /* Number of tile ids per phase (ids 1..count). */

@@ -36,10 +36,10 @@ struct Resolved {
   KParams kp;
   int ltile, gtile, halo;
   int lth, ltw, gth, gtw;
-  bool lstream, gstream;   // streaming kernels (tile ids 5-7) or LDS tile kernels (ids 1-4)
+  bool lstream, gstream;   // streaming kernels (tile ids 5 and up) or LDS tile kernels (ids 1-4)
 };
 
-constexpr int kTileIdsLocal = 9;
+constexpr int kTileIdsLocal = 10;   // ids 5-10 streaming (10: 96 rows)
 constexpr int kTileIdsGlobal = 9;   // ids 8, 9: 16- and 8-row streaming tiles, default chain only
 
 bool odd_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v % 2) == 1; }

@@ -175,22 +175,46 @@ __device__ __forceinline__ void for_slots(F&& f) {
 // to the tile's first row (low 16 bits; kRecNone: none) and the 32-row bands
 // of the tile that hold an empty row after it (high 16 bits, bit b: band b).
 constexpr int kRecNone = 0xffff;
-__device__ __forceinline__ unsigned short record_first(int first, int ty0) {
-  return (unsigned short)(first == kNoTop ? kRecNone : first - ty0);
-}
 
 // ---------------------------------------------------------------------------
 // Phase 1, streaming: stages 1-4 for 108 x TH output cells per wave.
 constexpr int kLocalHalo = 10;                         // >= RD + 2 + 2 + 3 for RD <= 3
 constexpr int kLocalTW = 2 * kLanes - 2 * kLocalHalo;  // 108
+// Word 3 of a raw buffer resource on gfx9-family chips (32-bit data format).
+constexpr int kBufferWord3 = 0x00020000;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+// 8-byte stores of column pairs (the streaming kernels' lanes own columns
+// 2 l + even offset): every row of the map starts 8-byte aligned.
+__device__ __forceinline__ bool pair_ok(int W, const void* map) {
+  return (W & 1) == 0 && (reinterpret_cast<unsigned long long>(map) & 7u) == 0;
+}
+
+// One band of a column's record: nz holds the non-empty flags of the band's
+// nb rows (the band's first row in bit nb - 1), vm those of them within the
+// frame.  Sets first (the tile-relative first non-empty row, kRecNone if
+// none yet) at the band's first non-empty row, and bit 16 + b of holes if
+// an empty row follows the column's first non-empty row within the band.
+__device__ __forceinline__ void resolve_band(unsigned nz, unsigned vm, int b, int nb, int& first, unsigned& holes) {
+  const unsigned ne = nz & vm, em = ~nz & vm;
+  const int p = 31 - __builtin_clz(ne | 1u);   // the band's first non-empty row is bit p
+  const bool seen = first != kRecNone;
+  const unsigned after = seen ? em : em & ((1u << p) - 1u);
+  holes |= ((seen || ne != 0u) && after != 0u) ? 0x10000u << b : 0u;
+  first = (!seen && ne != 0u) ? 32 * b + (nb - 1 - p) : first;
+}
 
 // Writes the stage-4 map into f.v4 for the later stages (the stage hooks
-// 1-4 take the LDS kernel).  The per-row work keeps to few scalar
-// instructions and no branch: row checks are one unsigned compare, the
-// column-top record is a running minimum, the hole bands a running or, and
-// the stores are unconditional, the lanes with nothing to store writing to a
-// scratch slot just past the map.
-template <int SHAPE, int RD, int TH>
+// 1-4 take the LDS kernel).  The per-row work keeps to few instructions and
+// no branch: loads and stores take the row's byte offset in a scalar
+// register and the lane's column offset in a vector one (buffer accesses),
+// and with PAIR (frames of even width, where a lane's two columns are an
+// 8-byte aligned pair, in or out of the frame together) one 8-byte store
+// writes both columns, so that a wave's output row is one contiguous store;
+// row checks are one unsigned compare; the column records are a shift
+// register of non-empty flags per column, resolved once per 32-row band;
+// and the stores are unconditional, the lanes with nothing to store writing
+// to a scratch slot just past the map.
+template <int SHAPE, int RD, int TH, bool PAIR>
 __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0, int tx0, int lane) {
   const int H = f.H, W = f.W;
   const float thr = kp.thr, off = kp.off;
@@ -208,6 +232,9 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   constexpr int D2 = RD, D3A = RD + 2, D3B = RD + 4, D4 = RD + 7;  // row delays of the stage outputs
   const int q0 = ty0 - D4;
   const int n = TH + 2 * D4;
+  // output row q0 + r - D4 = ty0 + r - 2 D4 ends a band (or the tile) at
+  // block slot (2 D4 - 1) & 7
+  constexpr int kResolve = (2 * D4 + 7) & 7;
 
   // ring buffers (slot = relative row & 7), ordering keys
   int h[8][RD + 1][2];        // stage-2 horizontal maxima per radius
@@ -224,32 +251,41 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
     hf[s][0] = hf[s][1] = 0;
     v3[s][0] = v3[s][1] = 0;
   }
-  int first_a = kNoTop, first_b = kNoTop;
-  gint* dst = gw(f.v4);
   // column records for the fill ahead of phase 2, written once at the end
-  // of the tile: the first non-empty row and the bands holding a hole
+  // of the tile: per column the non-empty flags of the current band's rows
+  // so far (newest in bit 0), the first non-empty row of the tile (relative
+  // to ty0; kRecNone: none yet) and the bands with a hole after it (bits 16..)
+  unsigned nz_a = 0u, nz_b = 0u, holes_a = 0u, holes_b = 0u;
+  int first_a = kRecNone, first_b = kRecNone;
   gchar* rec = (gchar*)(char*)f.v6p + 4 * (size_t)(ty0 / TH) * W;   // uniform row base; lanes add ua / ub
-  gcfloat* in = gcf(f.in);
+  // byte offsets within a map are below 2^32 (H W < 2^30)
+  const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc((void*)f.in, (short)0, -1, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc((void*)f.v4, (short)0, -1, kBufferWord3);
   const unsigned W4 = 4u * (unsigned)W;
   const unsigned sink = sink_offset(H, W);               // scratch slot past the stage-4 map
   const unsigned uH = (unsigned)H;
 
-  // input rows are fetched 4 rows ahead of their use (a wave's row step
-  // takes about a microsecond; fewer registers keep five waves per SIMD)
+  // input rows are fetched 4 rows ahead of their use (fewer registers keep
+  // five waves per SIMD)
   float da[4], db[4];
-  // bands of the lane's columns that hold a hole (record bits 16..), set
-  // without a branch in the row loop
-  unsigned holes_a = 0u, holes_b = 0u;
   auto fetch = [&](int r, float& xa_, float& xb_) {
-    const unsigned rowoff = (unsigned)clampi_s(q0 + r, 0, H - 1) * W4;
-    xa_ = ldf(in, rowoff + la);
-    xb_ = ldf(in, rowoff + lb);
+    const int rowoff = (int)((unsigned)clampi_s(q0 + r, 0, H - 1) * W4);
+    xa_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, (int)la, rowoff, 0));
+    xb_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, (int)lb, rowoff, 0));
   };
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     fetch(u, da[u], db[u]);
     __builtin_amdgcn_sched_barrier(0);   // keep the prefetch in row order
   }
+  // As many stores per prefetched row to the scratch slots past the map as
+  // a row step makes: the row loop is entered with as many memory
+  // operations in flight as in its steady state, so the waits at the top of
+  // its blocks keep the full prefetch distance (vector memory operations
+  // complete in order, and the compiler waits for the fewer in flight of the
+  // loop's two entries).
+#pragma unroll
+  for (int k = 0; k < (PAIR ? 4 : 8); ++k) __builtin_amdgcn_raw_buffer_store_b32(0u, dst, 0, (int)(sink + 4u * k), 0);
 
   // Whole blocks of 8 rows: the steps past row n compute values no row
   // stores (their rows are past the tile), which keeps the unrolled block
@@ -264,13 +300,15 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
       int va, vb;
       {
         const bool rin = (unsigned)q < uH;
-        const float x0 = detachf(da[u & 3]), x1 = detachf(db[u & 3]);
-        const float d0 = (rin && ina) ? x0 : 0.f, d1 = (rin && inb) ? x1 : 0.f;
+        const float d0 = detachf(da[u & 3]), d1 = detachf(db[u & 3]);
         fetch(r + 4, da[u & 3], db[u & 3]);
         __builtin_amdgcn_sched_barrier(0);   // issue the prefetch here, four rows ahead
+        // cells outside the frame are empty (the loads read a clamped cell);
+        // with a finite offset, min(d, off - d) > thr is d > thr and
+        // off - d > thr (a NaN fails both)
         const float v0 = off - d0, v1 = off - d1;
-        va = fminf(d0, v0) > thr ? key(v0) : 0;
-        vb = fminf(d1, v1) > thr ? key(v1) : 0;
+        va = (rin && ina && d0 > thr && v0 > thr) ? key(v0) : 0;
+        vb = (rin && inb && d1 > thr && v1 > thr) ? key(v1) : 0;
       }
 
       // Stage 2: kernel dilation; horizontal maxima of row q, then the
@@ -340,7 +378,8 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         hf[u][1] = max(t, RRa);
       }
       const int o4 = q - D4;
-      const bool o4row = o4 >= ty0 && o4 < ty0 + TH && o4 < H;
+      const int o4rel = o4 - ty0;
+      const bool o4row = o4rel >= 0 && o4rel < TH && o4 < H;
       int oa, ob;
       {
         const int ma = max3i(max3i(hf[(u - 6) & 7][0], hf[(u - 5) & 7][0], hf[(u - 4) & 7][0]),
@@ -350,26 +389,39 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
         const int c3a = v3[(u - 3) & 7][0], c3b = v3[(u - 3) & 7][1];
         oa = c3a <= kthr ? ma : c3a;
         ob = c3b <= kthr ? mb : c3b;
-        // rows arrive in order, so the first non-empty row is a running minimum
-        const int cand = o4row ? o4 : kNoTop;
-        const int cand_a = outa ? cand : kNoTop, cand_b = outb ? cand : kNoTop;
-        first_a = min(first_a, oa > kthr ? cand_a : kNoTop);
-        first_b = min(first_b, ob > kthr ? cand_b : kNoTop);
-        // an empty cell below the column's first non-empty row of the tile:
-        // oa <= kthr and first_a < o4, as one signed compare
-        const unsigned bit = (0x10000u << (((unsigned)(o4 - ty0) >> 5) & 15u)) & (o4row ? ~0u : 0u);
-        holes_a |= max(oa - kthr - 1, (int)((unsigned)first_a - (unsigned)o4)) < 0 ? bit : 0u;
-        holes_b |= max(ob - kthr - 1, (int)((unsigned)first_b - (unsigned)o4)) < 0 ? bit : 0u;
+        nz_a = nz_a + nz_a + (oa > kthr ? 1u : 0u);
+        nz_b = nz_b + nz_b + (ob > kthr ? 1u : 0u);
       }
-      const unsigned ro = (unsigned)o4 * W4;
-      stk(dst, (o4row && outa) ? ro + ua : sink, oa);
-      stk(dst, (o4row && outb) ? ro + ub : sink, ob);
+      {
+        const unsigned row = o4row ? (unsigned)o4 * W4 : sink;
+        if constexpr (PAIR) {
+          u32x2 v;
+          v.x = (unsigned)oa;
+          v.y = (unsigned)ob;
+          __builtin_amdgcn_raw_buffer_store_b64(v, dst, (int)((o4row && outa) ? ua : sink - row), (int)row, 0);
+        } else {
+          __builtin_amdgcn_raw_buffer_store_b32((unsigned)oa, dst, (int)((o4row && outa) ? ua : sink - row),
+                                                (int)row, 0);
+          __builtin_amdgcn_raw_buffer_store_b32((unsigned)ob, dst, (int)((o4row && outb) ? ub : sink - row),
+                                                (int)row, 0);
+        }
+      }
+      // the last row of a band (or of the tile): its rows within the frame
+      // give the first non-empty row and whether an empty row follows it
+      if (u == kResolve && o4rel >= 0 && o4rel < TH && ((o4rel & 31) == 31 || o4rel == TH - 1)) {
+        const int b = o4rel >> 5;
+        const int nb = o4rel - 32 * b + 1;                    // rows of the band
+        const int nv = clampi_s(H - ty0 - 32 * b, 0, nb);    // of them within the frame
+        const unsigned vm = nv == 0 ? 0u : (0xffffffffu >> (32 - nv)) << (nb - nv);
+        resolve_band(nz_a, vm, b, nb, first_a, holes_a);
+        resolve_band(nz_b, vm, b, nb, first_b, holes_b);
+      }
     }
   }
-  if (outa && first_a != kNoTop) atomic_min_g(f.top + ca, first_a);
-  if (outb && first_b != kNoTop) atomic_min_g(f.top + cb, first_b);
-  if (outa) stk((gint*)rec, ua, (int)(holes_a | record_first(first_a, ty0)));
-  if (outb) stk((gint*)rec, ub, (int)(holes_b | record_first(first_b, ty0)));
+  if (outa && first_a != kRecNone) atomic_min_g(f.top + ca, ty0 + first_a);
+  if (outb && first_b != kRecNone) atomic_min_g(f.top + cb, ty0 + first_b);
+  if (outa) stk((gint*)rec, ua, (int)(holes_a | (unsigned)first_a));
+  if (outb) stk((gint*)rec, ub, (int)(holes_b | (unsigned)first_b));
 }
 
 template <int SHAPE, int RD, int TH>
@@ -383,7 +435,8 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(5))) voi
     f = uniform_frame(f);
     const int lt = t - f.ltile0;
     const int tr = lt / f.lcols;
-    local_stream_tile<SHAPE, RD, TH>(f, kp, tr * TH, (lt - tr * f.lcols) * kLocalTW, lane);
+    if (pair_ok(f.W, f.v4)) local_stream_tile<SHAPE, RD, TH, true>(f, kp, tr * TH, (lt - tr * f.lcols) * kLocalTW, lane);
+    else local_stream_tile<SHAPE, RD, TH, false>(f, kp, tr * TH, (lt - tr * f.lcols) * kLocalTW, lane);
   }
 }
 
@@ -758,7 +811,7 @@ __device__ __forceinline__ void global_stream_tile(const FrameDesc& f, const KPa
 // same outputs.  They are computed once from the top cells and stored to
 // those rows; the streaming loop runs over the remaining rows (a multiple
 // of 8, from the tile's end) only.
-template <int TH, bool INTERIOR>
+template <int TH, bool INTERIOR, bool PAIR>
 __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParams& kp, int ty0, int tx0, int lane) {
   static_assert(TH % 8 == 0, "tile rows");
   const int H = f.H, W = f.W;
@@ -775,6 +828,22 @@ __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParam
   gcint* v4 = gc(f.v4);
   gint* out = gw(f.out);
   const unsigned W4 = 4u * (unsigned)W;
+  // output row stores: with PAIR (even W: a lane's two columns are an 8-byte
+  // aligned pair, in or out of the frame together) one 8-byte store per lane
+  const __amdgpu_buffer_rsrc_t orsrc = __builtin_amdgcn_make_buffer_rsrc((void*)f.out, (short)0, -1, kBufferWord3);
+  auto put = [&](unsigned ro, int va, int vb) __attribute__((always_inline)) {
+    if constexpr (PAIR) {
+      if (outa) {
+        u32x2 v;
+        v.x = (unsigned)va;
+        v.y = (unsigned)vb;
+        __builtin_amdgcn_raw_buffer_store_b64(v, orsrc, (int)ua, (int)ro, 0);
+      }
+    } else {
+      if (outa) stk(out, ro + ua, va);
+      if (outb) stk(out, ro + ub, vb);
+    }
+  };
   // Stage 5 on load: a row above its column's top reads the top cell,
   // V5[y][x] = V4[max(y, top)][x]; as byte offsets, the larger of the row's
   // and the top cell's (0 without a top or without the extension).
@@ -826,11 +895,7 @@ __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParam
     // the vertical taps sum to 16: (16 h) / 256 = h / 16, exactly
     const int oa = key(ma ? off - (float)(ha * (1.0 / 16.0)) : 0.f);
     const int ob = key(mb ? off - (float)(hb * (1.0 / 16.0)) : 0.f);
-    for (int g = ty0; g < r_start; ++g) {
-      const unsigned ro = (unsigned)g * W4;
-      if (outa) stk(out, ro + ua, oa);
-      if (outb) stk(out, ro + ub, ob);
-    }
+    for (int g = ty0; g < r_start; ++g) put((unsigned)g * W4, oa, ob);
     if (r_start == ty0 + TH) return;
   }
   const int q0 = r_start - 4;           // first input row; step s takes rows q0 + 2s, q0 + 2s + 1
@@ -949,9 +1014,7 @@ __device__ __forceinline__ void rows_first_tile(const FrameDesc& f, const KParam
               const bool ma = mk[k][0] > kthr, mb = mk[k][1] > kthr;
               const float oa = ma ? off - (float)(ga * (1.0 / 256.0)) : 0.f;
               const float ob = mb ? off - (float)(gb * (1.0 / 256.0)) : 0.f;
-              const unsigned ro = (unsigned)g * W4;
-              if (outa) stk(out, ro + ua, key(oa));
-              if (outb) stk(out, ro + ub, key(ob));
+              put((unsigned)g * W4, key(oa), key(ob));
             }
           }
         }
@@ -1035,9 +1098,11 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (pos < cap) gw(slow)[lds_queue_offset(cap) + pos] = t;
       }
     } else if (ty0 >= 4 && ty0 + TH + 2 <= f.H) {
-      rows_first_tile<TH, true>(f, kp, ty0, tx0, lane);
+      if (pair_ok(f.W, f.out)) rows_first_tile<TH, true, true>(f, kp, ty0, tx0, lane);
+      else rows_first_tile<TH, true, false>(f, kp, ty0, tx0, lane);
     } else {
-      rows_first_tile<TH, false>(f, kp, ty0, tx0, lane);
+      if (pair_ok(f.W, f.out)) rows_first_tile<TH, false, true>(f, kp, ty0, tx0, lane);
+      else rows_first_tile<TH, false, false>(f, kp, ty0, tx0, lane);
     }
   }
 }
@@ -1563,7 +1628,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 constexpr int stream_local_rows(int id) {
-  return id == 5 ? 64 : id == 6 ? 128 : id == 7 ? 32 : id == 8 ? 16 : id == 9 ? 8 : 0;
+  return id == 5 ? 64 : id == 6 ? 128 : id == 7 ? 32 : id == 8 ? 16 : id == 9 ? 8 : id == 10 ? 96 : 0;
 }
 constexpr int stream_global_rows(int id) {
   return id == 5 ? 64 : id == 6 ? 32 : id == 7 ? 128 : id == 8 ? 16 : id == 9 ? 8 : 0;
@@ -1595,7 +1660,8 @@ bool stream_global_supported(int rm, int rg) { return (rm == 0 || rm == 2) && rg
   X(2, 2, 5) X(1, 2, 5) X(0, 2, 5) X(3, 2, 5) X(0, 1, 5) X(0, 3, 5) X(2, 2, 6) X(2, 2, 7) \
   X(1, 2, 6) X(0, 2, 6) X(3, 2, 6) X(0, 1, 6) X(0, 3, 6) X(1, 2, 7) X(0, 2, 7) X(3, 2, 7) X(0, 1, 7) X(0, 3, 7) \
   X(2, 2, 8) X(1, 2, 8) X(0, 2, 8) X(3, 2, 8) X(0, 1, 8) X(0, 3, 8) \
-  X(2, 2, 9) X(1, 2, 9) X(0, 2, 9) X(3, 2, 9) X(0, 1, 9) X(0, 3, 9)
+  X(2, 2, 9) X(1, 2, 9) X(0, 2, 9) X(3, 2, 9) X(0, 1, 9) X(0, 3, 9) \
+  X(2, 2, 10) X(1, 2, 10) X(0, 2, 10) X(3, 2, 10) X(0, 1, 10) X(0, 3, 10)
 
 hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
 #define X(S, R, ID)                                                                                        \

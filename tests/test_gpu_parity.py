@@ -130,7 +130,7 @@ def test_param_variants(i):
     assert_all_stages(synth.random_map(rng, 37, 70, 0.03, 1.0, 79.0), p, tag=f"variant {i} random")
 
 
-@pytest.mark.parametrize("tl", [1, 2, 3, 4, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("tl", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 @pytest.mark.parametrize("tg", [1, 4, 5, 6, 7])
 def test_tile_shapes(tl, tg):
     p = api.Params(tile_local=tl, tile_global=tg)
@@ -139,12 +139,12 @@ def test_tile_shapes(tl, tg):
     assert_all_stages(f.sparse, p, stages=(4, 5, 6, 7, 9), tag=f"tiles {tl}/{tg}")
 
 
-@pytest.mark.parametrize("tl", [8, 9])
+@pytest.mark.parametrize("tl", [8, 9, 10])
 @pytest.mark.parametrize("i", range(8))
 def test_short_phase1_tiles_every_dilation(i, tl):
     """Phase-1 tile ids 8 and 9 (16 and 8 rows: one record band per tile)
-    with each dilation the streaming phase 1 serves, on frames spanning
-    several tile rows and a ragged last one."""
+    and 10 (96 rows: three bands) with each dilation the streaming phase 1
+    serves, on frames spanning several tile rows and a ragged last one."""
     p = dataclasses.replace(VARIANTS[i], tile_local=tl)
     if api.workspace_bytes(150, 300, p) == 0:
         # a chain the streaming phase 1 does not serve, at any tile height
@@ -156,7 +156,7 @@ def test_short_phase1_tiles_every_dilation(i, tl):
 
 
 @pytest.mark.parametrize("tg", [8, 9])
-@pytest.mark.parametrize("tl", [0, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("tl", [0, 5, 6, 7, 8, 9, 10])
 def test_short_phase2_tiles(tl, tg):
     """Phase-2 tile ids 8 and 9 (16 and 8 rows, the default chain only;
     stage hooks run the general phase 2 on 32-row tiles), alone and in a
@@ -267,7 +267,7 @@ def fill_case_map(seed):
     return m
 
 
-@pytest.mark.parametrize("tl", [0, 5, 6, 7])
+@pytest.mark.parametrize("tl", [0, 5, 6, 7, 10])
 def test_fill_ahead_of_phase2_cases(tl):
     """The default chain fills the cells empty after stage 5 ahead of phase 2
     (per cell for a few, per band separably for many): bit-exact."""
@@ -352,16 +352,15 @@ def test_rows_above_every_top(case, tg):
     assert_stage_equal(got, want, f"{case} tile {tg}")
 
 
-@pytest.mark.parametrize("tl", [5, 6, 7, 8, 9])
+@pytest.mark.parametrize("tl", [5, 6, 7, 8, 9, 10])
 @pytest.mark.parametrize("case", ["first_row_0", "first_row_13", "first_row_100", "first_row_170",
                                   "last_row_only", "garbage_on_top", "all_empty", "full7", "full3"])
 def test_empty_rows_on_top(case, tl):
-    """Phase 1 stores the output rows whose window holds no input value as
-    zeros and starts streaming just above the first value: bit-exact against
-    the oracle for every phase-1 tile height, first values at and between
-    tile boundaries, a frame with values in its last row only, garbage that
-    is not zero (NaN, negatives, depths beyond the offset) above the first
-    valid row, an empty frame, and other dilation radii."""
+    """Frames whose top rows hold no value: bit-exact against the oracle for
+    every streaming phase-1 tile, with first values at and between tile
+    boundaries, a frame with values in its last row only, garbage that is
+    not zero (NaN, negatives, depths beyond the offset) above the first valid
+    row, an empty frame, and other dilation radii."""
     H, W = 300, 460
     p = dataclasses.replace(api.Params(), tile_local=tl)
     rng = np.random.default_rng([58, tl, len(case)])
@@ -386,3 +385,27 @@ def test_empty_rows_on_top(case, tl):
     want = oracle.complete_map(m, oracle_params(p))
     got = gpu_stage(m, 9, p)
     assert_stage_equal(got, want, f"{case} tile {tl}")
+
+
+@pytest.mark.parametrize("shape", [(133, 290), (64, 1242), (75, 301)])
+def test_output_not_8_byte_aligned(shape):
+    """Even-width frames store column pairs with 8-byte stores when the
+    output starts 8-byte aligned; an output (and input) view 4 bytes off
+    that alignment takes 4-byte stores: both equal the oracle, batched too."""
+    H, W = shape
+    f = synth.lidar_frame(H, W, seed=[59, H, W], n_rows=32, density=0.05).sparse
+    want = oracle.complete_map(f)
+    big_in = torch.zeros(H * W + 1, dtype=torch.float32, device=DEV)
+    big_out = torch.zeros(H * W + 1, dtype=torch.float32, device=DEV)
+    src = big_in[1:].view(H, W)
+    src.copy_(torch.from_numpy(f))
+    dst = big_out[1:].view(H, W)
+    assert dst.data_ptr() % 8 == 4
+    api.complete(src, out=dst)
+    assert_stage_equal(dst.cpu().numpy(), want, f"{shape} unaligned")
+    aligned = api.complete(torch.from_numpy(f).to(DEV))
+    assert_stage_equal(aligned.cpu().numpy(), want, f"{shape} aligned")
+    outs = [big_out[1:].view(H, W), torch.empty(H, W, device=DEV)]
+    api.complete_batch([src, src.clone()], api.Params(), outs=outs)
+    for o in outs:
+        assert_stage_equal(o.cpu().numpy(), want, f"{shape} batch")
