@@ -228,7 +228,9 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   // issued unconditionally (the values of outside columns are masked where
   // they are used); loads issued on every path let the compiler wait for
   // each row alone instead of draining the prefetch
-  const unsigned la = 4u * (unsigned)clampi_s(ca, 0, W - 1), lb = 4u * (unsigned)clampi_s(cb, 0, W - 1);
+  // (PAIR: the pair's first column, clamped to 0 .. W - 2)
+  const unsigned la = 4u * (unsigned)clampi_s(ca, 0, PAIR ? W - 2 : W - 1);
+  const unsigned lb = 4u * (unsigned)clampi_s(cb, 0, W - 1);
   constexpr int D2 = RD, D3A = RD + 2, D3B = RD + 4, D4 = RD + 7;  // row delays of the stage outputs
   const int q0 = ty0 - D4;
   const int n = TH + 2 * D4;
@@ -270,8 +272,16 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   float da[4], db[4];
   auto fetch = [&](int r, float& xa_, float& xb_) {
     const int rowoff = (int)((unsigned)clampi_s(q0 + r, 0, H - 1) * W4);
-    xa_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, (int)la, rowoff, 0));
-    xb_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, (int)lb, rowoff, 0));
+    if constexpr (PAIR) {
+      // both cells at one column offset (a register copy made here, so that
+      // the + 4 stays an immediate): the compiler issues one 8-byte load
+      const int lo = detach((int)la);
+      xa_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, lo, rowoff, 0));
+      xb_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, lo + 4, rowoff, 0));
+    } else {
+      xa_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, (int)la, rowoff, 0));
+      xb_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, (int)lb, rowoff, 0));
+    }
   };
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
