@@ -1250,8 +1250,11 @@ __device__ __forceinline__ void fill_region(const FrameDesc& f, const KParams& k
       for (int k = 0; k < N; ++k)
         if (r0 + k < sr) S[(r0 + k) * kDW + cc] = (colin && (unsigned)(yb + k) < (unsigned)H) ? max(v[k], 0) : 0;
     };
-    stage(tid & 127, (tid >> 7) * RA, std::integral_constant<int, RA>{});
-    if (tid < GB * NB) stage(128 + tid % NB, (tid / NB) * RB, std::integral_constant<int, RB>{});
+    // (columns from ncols + 2 rl on feed only outputs past ncols, which are
+    // not used: they are not staged)
+    if ((tid & 127) < ncols + 2 * rl) stage(tid & 127, (tid >> 7) * RA, std::integral_constant<int, RA>{});
+    if (tid < GB * NB && 128 + tid % NB < ncols + 2 * rl)
+      stage(128 + tid % NB, (tid / NB) * RB, std::integral_constant<int, RB>{});
   }
   __syncthreads();
   // the region's cells that are empty after stage 5, one column per thread
@@ -1265,7 +1268,7 @@ __device__ __forceinline__ void fill_region(const FrameDesc& f, const KParams& k
   // staged values once every row has been read
   {
     const int rr = tid & (kLanes - 1), j0 = (tid / kLanes) * 32;   // a wave per run: lanes 158 ints apart
-    const bool act = rr < sr;
+    const bool act = rr < sr && j0 < ncols;
     int o[32];
     if (act) {
       if (rl == kFillRad) {
@@ -1456,7 +1459,9 @@ __global__ __launch_bounds__(kLanes) void k_fill_scan(FrameSource src, KParams k
   }
 }
 
-constexpr int kFillSparse = 48;   // cells of a band filled one by one; beyond: separably
+// cells of a band filled one by one; beyond: separably (a staged band costs
+// about as much as eight 31x31 windows read cell by cell)
+constexpr int kFillSparse = 8;
 constexpr int kFillScan = 2048;   // hole rows of a band checked one by one; beyond: separably
 
 // window_max for up to NC cells of one phase-1 tile at once (pos: y * W + x,
