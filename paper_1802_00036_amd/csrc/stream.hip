@@ -1578,17 +1578,25 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         const int j = atomicAdd(&s_n, 1);
         if (j < kFillSparse) s_list[j] = (y0 + r) * W + x;
       }
-      // hole rows: the band's rows of every hole column, flattened over the threads
-      const int nh = s_nh, nb = b1 - b0;
-#pragma unroll 4
-      for (int idx = tid; idx < nh * nb; idx += kDenseThreads) {
-        const int k = idx / nb, r = b0 + idx - k * nb;
-        const int c = s_hcol[k];
-        const int y = y0 + r, xx = x0 + c;
-        const int v = v4[(size_t)y * W + xx];
-        if (r >= s_hfirst[k] && v <= kthr) {
-          const int j = atomicAdd(&s_n, 1);
-          if (j < kFillSparse) s_list[j] = y * W + xx;
+      // hole rows: the band's rows of every hole column, flattened over the
+      // threads, four per thread at a time; a thread stops once the band has
+      // more than kFillSparse cells (it is then filled separably)
+      const int nh = s_nh, nb = b1 - b0, total = nh * nb;
+      for (int base = 0; base < total; base += 4 * kDenseThreads) {
+        if (*(volatile int*)&s_n > kFillSparse) break;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int idx = base + u * kDenseThreads + tid;
+          if (idx < total) {
+            const int k = idx / nb, r = b0 + idx - k * nb;
+            const int c = s_hcol[k];
+            const int y = y0 + r, xx = x0 + c;
+            const int v = v4[(size_t)y * W + xx];
+            if (r >= s_hfirst[k] && v <= kthr) {
+              const int j = atomicAdd(&s_n, 1);
+              if (j < kFillSparse) s_list[j] = y * W + xx;
+            }
+          }
         }
       }
       __syncthreads();
