@@ -165,7 +165,6 @@ hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int t
 hipError_t launch_prefill(const FrameSource& src, const KParams& kp, int local_rows, int scan_grid, int tile_grid,
                           hipStream_t s);
 bool fast_chain(const KParams& kp);
-int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast);
 int prefill_resident_blocks();
 hipError_t launch_local(const FrameSource& src, const KParams& kp, int tile_id, int halo,
                         int grid, hipStream_t s);

@@ -434,11 +434,18 @@ __device__ void local_stream_tile(const FrameDesc& f, const KParams& kp, int ty0
   if (outb) stk((gint*)rec, ub, (int)(holes_b | (unsigned)first_b));
 }
 
+// Four waves per workgroup, one tile each: the waves of a workgroup go to
+// the four SIMDs of a compute unit, so 4 k tiles per compute unit put k
+// waves on every SIMD (single-wave workgroups were placed 2 to 4 per SIMD
+// for 3 on average, and the SIMDs with 4 set the launch's time).
+constexpr int kLocalWaves = 4;
+
 template <int SHAPE, int RD, int TH>
-__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(5))) void k_local_stream(FrameSource src, KParams kp) {
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(kLanes * kLocalWaves) __attribute__((amdgpu_waves_per_eu(5))) void k_local_stream(FrameSource src, KParams kp) {
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int wave = uni((int)threadIdx.x / kLanes);
   const int total = src.plan ? src.plan->ltiles : src.single_ltiles;
-  for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+  for (int t = xcd_tile_s(blockIdx.x, gridDim.x) * kLocalWaves + wave; t < total; t += gridDim.x * kLocalWaves) {
     FrameDesc f;
     if (src.plan) f = plan_frame(src, gc(src.plan->ltab)[t]);
     else f = src.single;
@@ -1657,12 +1664,6 @@ constexpr int stream_global_rows(int id) {
   return id == 5 ? 64 : id == 6 ? 32 : id == 7 ? 128 : id == 8 ? 16 : id == 9 ? 8 : 0;
 }
 
-template <class K>
-int occupancy_s(K kernel) {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kLanes, 0) != hipSuccess) return 1;
-  return nb > 0 ? nb : 1;
-}
 
 }  // namespace
 
@@ -1687,11 +1688,14 @@ bool stream_global_supported(int rm, int rg) { return (rm == 0 || rm == 2) && rg
   X(2, 2, 10) X(1, 2, 10) X(0, 2, 10) X(3, 2, 10) X(0, 1, 10) X(0, 3, 10)
 
 hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int tile_id, int grid, hipStream_t s) {
-#define X(S, R, ID)                                                                                        \
-  if (kp.shape == S && kp.rd == R && tile_id == ID) {                                                      \
-    hipLaunchKernelGGL((k_local_stream<S, R, stream_local_rows(ID)>), dim3(grid), dim3(kLanes), 0, s, src, \
-                       kp);                                                                                \
-    return hipGetLastError();                                                                              \
+  // grid: one wave per tile; workgroups of kLocalWaves waves, a multiple of
+  // the 8 XCDs of them
+  const int wgs = ((grid + kLocalWaves - 1) / kLocalWaves + 7) / 8 * 8;
+#define X(S, R, ID)                                                                                          \
+  if (kp.shape == S && kp.rd == R && tile_id == ID) {                                                        \
+    hipLaunchKernelGGL((k_local_stream<S, R, stream_local_rows(ID)>), dim3(wgs), dim3(kLanes * kLocalWaves), 0, \
+                       s, src, kp);                                                                          \
+    return hipGetLastError();                                                                                \
   }
   IPB_STREAM_LOCAL(X)
 #undef X
@@ -1761,20 +1765,5 @@ bool fast_chain(const KParams& kp) {
          kp.gw[1] == 4.0 && kp.gw[2] == 1.0 && kp.gscale == 1.0 / 256.0;
 }
 
-int stream_resident_blocks(int phase, int tile_id, const KParams& kp, bool fast) {
-  if (phase == 1) {
-#define X(S, R, ID) \
-  if (kp.shape == S && kp.rd == R && tile_id == ID) return occupancy_s(k_local_stream<S, R, stream_local_rows(ID)>);
-    IPB_STREAM_LOCAL(X)
-#undef X
-    return 1;
-  }
-  if (tile_id == 5) return fast ? occupancy_s(k_global_rows<64>) : occupancy_s(k_global_stream<64>);
-  if (tile_id == 6) return fast ? occupancy_s(k_global_rows<32>) : occupancy_s(k_global_stream<32>);
-  if (tile_id == 7) return fast ? occupancy_s(k_global_rows<128>) : occupancy_s(k_global_stream<128>);
-  if (tile_id == 8 && fast) return occupancy_s(k_global_rows<16>);
-  if (tile_id == 9 && fast) return occupancy_s(k_global_rows<8>);
-  return 1;
-}
 
 }  // namespace ipb
