@@ -1098,12 +1098,14 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) voi
 // kernel.  Up to 168 registers (three waves per SIMD): the row windows,
 // the pair merge and the ring of sums stay in registers.
 template <int TH>
-__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3))) void k_global_rows(FrameSource src, KParams kp) {
-  const int lane = threadIdx.x;
+// (four waves per workgroup, one tile each, as k_local_stream)
+__global__ __launch_bounds__(kLanes * kLocalWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_global_rows(FrameSource src, KParams kp) {
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int wave = uni((int)threadIdx.x / kLanes);
   const int total = src.plan ? src.plan->gtiles : src.single_gtiles;
   int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
-  for (int t = xcd_tile_s(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+  for (int t = xcd_tile_s(blockIdx.x, gridDim.x) * kLocalWaves + wave; t < total; t += gridDim.x * kLocalWaves) {
     FrameDesc f = src.plan ? plan_frame(src, gc(src.plan->gtab)[t]) : src.single;
     f = uniform_frame(f);
     const int gt = t - f.gtile0;
@@ -1704,16 +1706,19 @@ hipError_t launch_local_stream(const FrameSource& src, const KParams& kp, int ti
 
 hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int tile_id, bool fast, int grid,
                                 hipStream_t s) {
-#define IPB_GS(TH)                                                                           \
-  if (fast) hipLaunchKernelGGL((k_global_rows<TH>), dim3(grid), dim3(kLanes), 0, s, src, kp); \
+  // k_global_rows: workgroups of kLocalWaves waves (a multiple of 8 of them)
+  const int wgs = ((grid + kLocalWaves - 1) / kLocalWaves + 7) / 8 * 8;
+  const dim3 rb(kLanes * kLocalWaves);
+#define IPB_GS(TH)                                                                       \
+  if (fast) hipLaunchKernelGGL((k_global_rows<TH>), dim3(wgs), rb, 0, s, src, kp);        \
   else hipLaunchKernelGGL((k_global_stream<TH>), dim3(grid), dim3(kLanes), 0, s, src, kp);
   if (tile_id == 5) { IPB_GS(64) }
   else if (tile_id == 6) { IPB_GS(32) }
   else if (tile_id == 7) { IPB_GS(128) }
   else if (tile_id == 8 && fast)   // 16- and 8-row tiles: the default chain only
-    hipLaunchKernelGGL((k_global_rows<16>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+    hipLaunchKernelGGL((k_global_rows<16>), dim3(wgs), rb, 0, s, src, kp);
   else if (tile_id == 9 && fast)
-    hipLaunchKernelGGL((k_global_rows<8>), dim3(grid), dim3(kLanes), 0, s, src, kp);
+    hipLaunchKernelGGL((k_global_rows<8>), dim3(wgs), rb, 0, s, src, kp);
   else return hipErrorInvalidValue;
 #undef IPB_GS
   return hipGetLastError();
