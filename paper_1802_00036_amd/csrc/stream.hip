@@ -2,7 +2,9 @@
 // 2018, Sec. III): one wave64 per tile, two neighbouring columns per lane,
 // rows streamed top to bottom through register ring buffers.  Neighbouring
 // columns come from the adjacent lanes by DPP row moves (wave_shr/wave_shl),
-// so the fast path uses no LDS and no barriers.
+// so the streaming kernels use no LDS and no barriers; k_local_stream and
+// k_global_rows run four such waves per workgroup, one tile each.  On frames
+// of even width a lane's column pair is one 8-byte access.
 //
 //   k_local_stream  : stages 1-4 (inversion, kernel dilation, 5x5 closing,
 //                     7x7 small fill); 128 input columns -> 108 output
