@@ -15,8 +15,9 @@ One step = one batch through all nine stages.  Inputs are resident in HBM;
 at least three buffer sets (input, output, workspace) are rotated so the
 256 MB Infinity Cache cannot serve a step from the previous one.  The timed
 batches of the batched workloads are spread over --streams streams (3 by
-default), each buffer set bound to one of them, so independent batches
-overlap; the same batches on one stream are timed and reported too.  Prints
+default), each buffer set bound to one of them and each stream on a
+hardware queue of its own, so independent batches overlap; the same batches
+on one stream are timed and reported too.  Prints
 one JSON line.
 """
 from __future__ import annotations
@@ -161,8 +162,9 @@ def valu_ceiling(kernel: str, workload: str, ms: float):
 class Batches:
     """Rotating buffer sets of one batch (inputs, outputs, workspace, device
     plan), each bound to one of n_streams streams (all at the default
-    priority).  Batches are independent, so batches on different streams may
-    run at once; a set is only ever used on its own stream."""
+    priority, each on a hardware queue of its own).  Batches are independent,
+    so batches on different streams may run at once; a set is only ever used
+    on its own stream."""
 
     def __init__(self, host_maps, params, n_streams=1):
         import torch
@@ -181,7 +183,9 @@ class Batches:
         if all(H >= 3 and W >= 3 for H, W in self.shapes):
             self.steps.remove(PHASES.index("k_global_slow"))
         self.px = sum(H * W for H, W in self.shapes)
-        self.streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+        # streams from torch's pool share a few hardware queues, at times two
+        # of them one queue, whose batches would then run one after the other
+        self.streams = api.queue_streams(n_streams, self.dev)
         n_sets = n_streams * -(-3 // n_streams)        # at least three, a multiple of the streams
         self.sets = []
         for k in range(n_sets):

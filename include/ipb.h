@@ -240,6 +240,24 @@ const char* ipb_status_string(int status);
 /* The hipError_t behind the calling thread's last IPB_ERR_HIP (0 if none). */
 int ipb_last_hip_error(void);
 
+/* A stream of the current device with a hardware queue of its own, for
+ * callers that keep several batches in flight.  The runtime maps ordinary
+ * streams onto a small pool of hardware queues (GPU_MAX_HW_QUEUES, 4 by
+ * default), so two of them can share one queue and run their batches one
+ * after the other; a stream created with a compute-unit mask always gets a
+ * queue of its own.  The mask names every compute unit, so kernels on the
+ * stream still use the whole device.  The stream is at the default
+ * priority and, as any stream created without flags, synchronises with the
+ * legacy null stream.  On success *stream holds the hipStream_t; the caller
+ * owns it and releases it with ipb_stream_destroy.  Returns
+ * IPB_ERR_INVALID_ARG for a null pointer (*stream is then untouched) and
+ * IPB_ERR_HIP if the runtime refuses (*stream is then null). */
+int ipb_stream_create(void** stream);
+
+/* Destroys a stream made by ipb_stream_create once its queued work has
+ * finished (as hipStreamDestroy).  IPB_ERR_INVALID_ARG for a null stream. */
+int ipb_stream_destroy(void* stream);
+
 /* Tile shapes (rows, cols) of a tile id for phase 1 (local) or 2 (global);
  * returns IPB_ERR_INVALID_ARG for an unknown id.  Id 0 = automatic.  Ids
  * 1-4 are LDS tiles, 5 and up streaming tiles (phase 1: 64, 128, 32, 16, 8

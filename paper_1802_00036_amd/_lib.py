@@ -88,6 +88,8 @@ _SIGS = {
                                        _P(ctypes.c_int)]),
     "ipb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ipb_last_hip_error": (ctypes.c_int, []),
+    "ipb_stream_create": (ctypes.c_int, [_P(ctypes.c_void_p)]),
+    "ipb_stream_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "ipb_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P(ctypes.c_int), _P(ctypes.c_int)]),
     "ipb_tile_count": (ctypes.c_int, [ctypes.c_int]),
 }

@@ -78,6 +78,33 @@ def _launch_stream(stream: Optional[torch.cuda.Stream], device: torch.device):
     return stream, True
 
 
+# streams with hardware queues of their own, per device index, made on
+# first request and kept for the life of the process
+_QUEUE_STREAMS: dict = {}
+
+
+def queue_streams(n: int, device=None) -> List[torch.cuda.ExternalStream]:
+    """`n` streams of `device` (default: the current one), each on a
+    hardware queue of its own (ipb_stream_create), for batches kept in
+    flight side by side.  Streams from torch's pool share the runtime's few
+    hardware queues, at times two of them one queue, and batches on a
+    shared queue run one after the other.  The streams are made once per
+    device and live as long as the process; every caller that asks for `n`
+    gets the first `n` of them, so independent users of one process share
+    them.  They synchronise with the legacy null stream, as any stream
+    created without flags does."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    have = _QUEUE_STREAMS.setdefault(idx, [])
+    lib = L.lib()
+    with torch.cuda.device(idx):
+        while len(have) < n:
+            h = ctypes.c_void_p()
+            L.check(lib.ipb_stream_create(ctypes.byref(h)), "ipb_stream_create")
+            have.append(torch.cuda.ExternalStream(h.value, device=torch.device("cuda", idx)))
+    return have[:n]
+
+
 def _record(stream: torch.cuda.Stream, *tensors: torch.Tensor) -> None:
     for t in tensors:
         t.record_stream(stream)

@@ -24,7 +24,7 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib as L
-from .api import Params, _check_map, _stream_handle, _workspace, frames_array
+from .api import Params, _check_map, _stream_handle, _workspace, frames_array, queue_streams
 
 Shape = Tuple[int, int]
 # the library's automatic tile rule, in waves (MI355X: 256 CUs x 4 SIMDs)
@@ -202,7 +202,8 @@ class GraphBatch:
 
 class GraphPipeline:
     """GraphBatch engines of one capacity, each on its own stream (all at the
-    default priority), taking batches in turn.  Frames of different batches
+    default priority, each on a hardware queue of its own: queue_streams),
+    taking batches in turn.  Frames of different batches
     share nothing, so up to `engines` batches run on the GPU at once: one
     batch's short latency-bound launch steps and kernel tails overlap the
     large kernels of the others, which carries more frames per second than
@@ -212,7 +213,8 @@ class GraphPipeline:
                  device: Optional[torch.device] = None, use_graph: bool = True):
         if engines < 1:
             raise ValueError("a pipeline needs at least one engine")
-        self.engines = [GraphBatch(capacity, params, device=device, use_graph=use_graph) for _ in range(engines)]
+        streams = queue_streams(engines, device)
+        self.engines = [GraphBatch(capacity, params, device=device, stream=s, use_graph=use_graph) for s in streams]
         self.turn = 0
 
     def next_stream(self) -> torch.cuda.Stream:

@@ -684,6 +684,31 @@ const char* ipb_status_string(int status) {
 
 int ipb_last_hip_error(void) { return g_last_hip; }
 
+int ipb_stream_create(void** stream) {
+  if (stream == nullptr) return IPB_ERR_INVALID_ARG;
+  *stream = nullptr;
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (ncu <= 0) return hip_fail(hipErrorInvalidDevice);
+  // every compute unit of the device: the mask only makes the runtime give
+  // the stream a hardware queue of its own, it narrows nothing
+  std::vector<uint32_t> mask((ncu + 31) / 32, 0xffffffffu);
+  if (ncu % 32 != 0) mask.back() = (1u << (ncu % 32)) - 1u;
+  hipStream_t s = nullptr;
+  e = hipExtStreamCreateWithCUMask(&s, static_cast<uint32_t>(mask.size()), mask.data());
+  if (e != hipSuccess) return hip_fail(e);
+  *stream = s;
+  return IPB_OK;
+}
+
+int ipb_stream_destroy(void* stream) {
+  if (stream == nullptr) return IPB_ERR_INVALID_ARG;
+  hipError_t e = hipStreamDestroy(static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? IPB_OK : hip_fail(e);
+}
+
 int ipb_tile_shape(int phase, int tile_id, int* rows, int* cols) {
   if (rows == nullptr || cols == nullptr) return IPB_ERR_INVALID_ARG;
   if (tile_id == 0) tile_id = phase == 1 ? 5 : 6;   // defaults of the streaming kernels

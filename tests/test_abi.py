@@ -96,6 +96,8 @@ def test_argument_checks_return_before_any_gpu_call():
     c.struct_size = 4
     assert _ws_call(c) == L.IPB_ERR_INVALID_ARG
     assert L.lib().ipb_complete(None, 4, 4, ctypes.byref(p), None, None) == L.IPB_ERR_INVALID_ARG
+    assert L.lib().ipb_stream_create(None) == L.IPB_ERR_INVALID_ARG
+    assert L.lib().ipb_stream_destroy(None) == L.IPB_ERR_INVALID_ARG
     assert L.lib().ipb_complete_ws(ctypes.c_void_p(FAKE), 4, 4, None, ctypes.c_void_p(FAKE + 4096),
                                    ctypes.c_void_p(FAKE + 8192), 1 << 20, None) == L.IPB_ERR_INVALID_ARG
 

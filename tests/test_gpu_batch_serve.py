@@ -366,11 +366,48 @@ def test_shipped_tuning_entry_is_found(tmp_path, monkeypatch):
     assert (p.tile_local, p.tile_global) == (table[key]["tile_local"], table[key]["tile_global"])
 
 
-def test_batches_in_flight_on_streams():
-    """Three batches in flight on three streams (each with its own outputs,
-    workspace and plan; the inputs shared, only read), several rounds as the
-    bench's timed pass runs them: every output bitwise equal to the frame
-    completed alone."""
+def test_queue_streams_have_queues_of_their_own():
+    """ipb_stream_create: three streams with distinct handles, made once per
+    device (a second request returns the same ones), whose work runs side by
+    side: three equal spin kernels, one per stream, end in well under the
+    time they take one after the other."""
+    qs = api.queue_streams(3)
+    assert len({s.cuda_stream for s in qs}) == 3
+    assert [s.cuda_stream for s in api.queue_streams(2)] == [s.cuda_stream for s in qs[:2]]
+
+    def spin(streams, cycles):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(qs[0])
+        for s in streams[1:]:
+            s.wait_event(a)
+        for s in streams:
+            with torch.cuda.stream(s):
+                torch.cuda._sleep(cycles)
+        for s in streams[1:]:
+            e = torch.cuda.Event()
+            e.record(s)
+            qs[0].wait_event(e)
+        b.record(qs[0])
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    spin(qs[:1], 1 << 20)
+    cycles = max(1 << 20, int((1 << 20) * 10.0 / spin(qs[:1], 1 << 20)))    # about 10 ms
+    one = spin(qs[:1], cycles)
+    three = spin(qs, cycles)
+    print(f"[queue streams] one spin {one:.2f} ms, three side by side {three:.2f} ms", flush=True)
+    assert three < 2.0 * one
+
+
+@pytest.mark.parametrize("kind", ["pool", "queue"])
+def test_batches_in_flight_on_streams(kind):
+    """Three batches in flight on three streams (torch's pool streams, or
+    streams with hardware queues of their own), each with its own outputs,
+    workspace and plan, the inputs shared and only read, several rounds as
+    the bench's timed pass runs them: every output bitwise equal to the
+    frame completed alone."""
     import ctypes
     from paper_1802_00036_amd import _lib as L
     lib = L.lib()
@@ -392,9 +429,10 @@ def test_batches_in_flight_on_streams():
         n, lt, gt, cols = (ctypes.c_int() for _ in range(4))
         lib.ipb_plan_totals(ph, ctypes.byref(n), ctypes.byref(lt), ctypes.byref(gt), ctypes.byref(cols))
         pd = torch.frombuffer(bytearray(ph.raw), dtype=torch.uint8).to(frames[0].device)
-        lanes.append((torch.cuda.Stream(), outs, ws, pd, lt.value, gt.value, cols.value))
+        st = torch.cuda.Stream() if kind == "pool" else api.queue_streams(3)[k]
+        lanes.append((st, outs, ws, pd, lt.value, gt.value, cols.value))
     torch.cuda.synchronize()
-    print("[in flight] 3 streams x 6 rounds", flush=True)
+    print(f"[in flight] 3 {kind} streams x 6 rounds", flush=True)
     for _ in range(6):
         for s, outs, ws, pd, lt, gt, cols in lanes:
             L.check(lib.ipb_complete_planned(ctypes.c_void_p(pd.data_ptr()), ctypes.byref(cp), -2, lt, gt, cols,
