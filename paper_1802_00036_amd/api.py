@@ -6,6 +6,7 @@ stream, the HIP kernels behind the C ABI do all of the completion.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import dataclasses
 from typing import List, Optional, Sequence
@@ -79,8 +80,20 @@ def _launch_stream(stream: Optional[torch.cuda.Stream], device: torch.device):
 
 
 # streams with hardware queues of their own, per device index, made on
-# first request and kept for the life of the process
+# first request and kept until the interpreter exits
 _QUEUE_STREAMS: dict = {}
+
+
+def _release_queue_streams() -> None:
+    # at interpreter exit, ahead of the runtime's own teardown (and of a
+    # profiler's, which has ended in a fault over streams still alive then)
+    lib = L.lib()
+    for idx, streams in list(_QUEUE_STREAMS.items()):
+        with torch.cuda.device(idx):
+            torch.cuda.synchronize()
+            for s in streams:
+                lib.ipb_stream_destroy(ctypes.c_void_p(s.cuda_stream))
+    _QUEUE_STREAMS.clear()
 
 
 def queue_streams(n: int, device=None) -> List[torch.cuda.ExternalStream]:
@@ -89,12 +102,14 @@ def queue_streams(n: int, device=None) -> List[torch.cuda.ExternalStream]:
     flight side by side.  Streams from torch's pool share the runtime's few
     hardware queues, at times two of them one queue, and batches on a
     shared queue run one after the other.  The streams are made once per
-    device and live as long as the process; every caller that asks for `n`
+    device and live until the interpreter exits; every caller that asks for `n`
     gets the first `n` of them, so independent users of one process share
     them.  They synchronise with the legacy null stream, as any stream
     created without flags does."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if not _QUEUE_STREAMS:
+        atexit.register(_release_queue_streams)
     have = _QUEUE_STREAMS.setdefault(idx, [])
     lib = L.lib()
     with torch.cuda.device(idx):
