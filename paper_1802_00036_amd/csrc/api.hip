@@ -191,7 +191,7 @@ int resolve_frames(const ipb_params* p, const ipb_frame* frames, int n, Resolved
 struct DeviceFacts {
   int cus = 0;
   int occ[3][8][2] = {};    // LDS kernels: [phase][tile id][halo 9/12]
-  int prefill_occ = 0;     // fill ahead of phase 2 (k_fill_tiles)
+  int prefill_occ[2] = {0, 0};   // fill ahead of phase 2 (k_fill_tiles; [1]: the 31x31 window's)
 };
 std::mutex g_dev_mu;
 DeviceFacts g_dev[64];
@@ -219,10 +219,11 @@ int resident(int dev, int phase, int tile, int halo) {
   return slot;
 }
 
-int prefill_res(int dev) {
+int prefill_res(int dev, const KParams& kp) {
+  const bool full = prefill_full_window(kp);
   std::lock_guard<std::mutex> g(g_dev_mu);
-  int& slot = g_dev[dev].prefill_occ;
-  if (slot == 0) slot = prefill_resident_blocks();
+  int& slot = g_dev[dev].prefill_occ[full ? 1 : 0];
+  if (slot == 0) slot = prefill_resident_blocks(full);
   return slot;
 }
 
@@ -431,7 +432,7 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
   if ((phase == -1 || phase == 2) && prefill) {
     // one scanning wave per phase-1 tile (those of the first tile row work);
     // one workgroup per queued band, at most the resident ones
-    const int tgrid = std::max(1, (int)std::min<long long>((long long)kBandsPerTile * max_lt, prefill_res(dev) * cus));
+    const int tgrid = std::max(1, (int)std::min<long long>((long long)kBandsPerTile * max_lt, prefill_res(dev, kp) * cus));
     e = launch_prefill(src, kp, r.lth, max_lt, tgrid, s);
     if (e != hipSuccess) return hip_fail(e);
   }

@@ -165,7 +165,10 @@ hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int t
 hipError_t launch_prefill(const FrameSource& src, const KParams& kp, int local_rows, int scan_grid, int tile_grid,
                           hipStream_t s);
 bool fast_chain(const KParams& kp);
-int prefill_resident_blocks();
+// whether the fill ahead of phase 2 takes the 31x31 window's kernel, and
+// the resident workgroups per CU of the kernel it takes
+bool prefill_full_window(const KParams& kp);
+int prefill_resident_blocks(bool full_window);
 hipError_t launch_local(const FrameSource& src, const KParams& kp, int tile_id, int halo,
                         int grid, hipStream_t s);
 hipError_t launch_global(const FrameSource& src, const KParams& kp, int tile_id,

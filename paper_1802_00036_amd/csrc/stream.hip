@@ -1210,11 +1210,13 @@ __device__ __forceinline__ void vhgw31(const int* a, int* out) {
 // the 31-wide window) replace them in place; each cell of the region that is
 // empty after stage 5 takes the vertical max of those (for the 31-row window:
 // the rows all the region's windows share, then the prefix and suffix maxima
-// at both ends) and is handed to out(y, x, value).
+// at both ends) and is handed to out(y, x, value).  TOPS: the caller has
+// already put the tops of the staged columns (x0 - rl + i, clamped into the
+// image) in s_top and passed a barrier since, and no thread still reads S.
 constexpr int kDW = kGlobalTW + 2 * kFillRad + 8;    // 158 staged columns (4 runs of 32 outputs + 30)
 constexpr int kDenseThreads = 256;
 
-template <int QR, class Out>
+template <int QR, bool TOPS, class Out>
 __device__ __forceinline__ void fill_region(const FrameDesc& f, const KParams& kp, int y0, int nr, int x0, int ncols,
                                             int* S, int* s_top, int tid, Out&& out) {
   static_assert(QR + 2 * kFillRad <= kLanes, "one staged row per lane for the horizontal maxima");
@@ -1222,12 +1224,14 @@ __device__ __forceinline__ void fill_region(const FrameDesc& f, const KParams& k
   const int kthr = key(kp.thr);
   gcint* v4 = gc(f.v4);
   const int sr = nr + 2 * rl;
-  __syncthreads();                                    // LDS of the previous region is no longer read
-  if (tid < kDW) {                                    // column tops of the staged columns (>= H: none)
-    const int x = clampi_s(x0 - rl + tid, 0, W - 1);
-    s_top[tid] = kp.extrapolate ? gc(f.top)[x] : H;
+  if constexpr (!TOPS) {
+    __syncthreads();                                  // LDS of the previous region is no longer read
+    if (tid < kDW) {                                  // column tops of the staged columns (>= H: none)
+      const int x = clampi_s(x0 - rl + tid, 0, W - 1);
+      s_top[tid] = kp.extrapolate ? gc(f.top)[x] : H;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   {
     // Each thread stages whole runs of one column, so the column's clamped x,
     // its top and whether it lies in the image are worked out once: columns
@@ -1364,7 +1368,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, K
     if (nr <= 0) continue;                      // a quarter past the last row (queued for its input rows)
     gint* v6p = gw(f.v6p);
     const int W = f.W;
-    fill_region<QR>(f, kp, y0, nr, tx0, ncols, S, s_top, tid,
+    fill_region<QR, false>(f, kp, y0, nr, tx0, ncols, S, s_top, tid,
                     [&](int y, int x, int m) { v6p[(size_t)y * W + x] = m; });
   }
 }
@@ -1475,6 +1479,76 @@ __global__ __launch_bounds__(kLanes) void k_fill_scan(FrameSource src, KParams k
 constexpr int kFillSparse = 8;
 constexpr int kFillScan = 2048;   // hole rows of a band checked one by one; beyond: separably
 
+// The fill of a band of nr <= kBandRows rows (from y0) and ncols <= 108
+// columns (from x0) for the 31x31 window, the vertical maxima first.  Each
+// staged column (x0 - 15 + i for i < ncols + 30) loads its 62 rows from
+// y0 - 15 into registers (stage 5 applied; cells outside the image and
+// tagged cells as 0, which no max selects over a non-empty value), keeps
+// the band's empty cells of its column as a bit mask and writes the maxima
+// of its 31-row windows at the band's rows to LDS (van Herk/Gil-Werman).
+// Each band row holding an empty cell then takes, 32 columns at a time, the
+// maxima of 31 of those across and hands the empty cells' values to
+// out(y, x, value).  The caller has put the staged columns' tops in s_top,
+// set *s_rows to 0 and passed a barrier since; no thread still reads S.
+constexpr int kDWV = 159;   // LDS row pitch: odd, so a row pass's lanes (one row each) hit distinct banks
+template <class Out>
+__device__ __forceinline__ void fill_band_vfirst(const FrameDesc& f, const KParams& kp, int y0, int nr, int x0,
+                                                 int ncols, int* S, const int* s_top, unsigned* s_em,
+                                                 unsigned* s_rows, int tid, Out&& out) {
+  constexpr int R = kFillRad, SRM = kBandRows + 2 * R;
+  static_assert(SRM == 62 && kBandRows == 32, "vhgw31 takes 62 values to 32 maxima");
+  static_assert(4 * 32 + 2 * R <= kDWV && kLocalTW <= 128 && kLocalTW + 2 * R <= kDenseThreads, "band layout");
+  const int H = f.H, W = f.W;
+  const int kthr = key(kp.thr);
+  gcint* v4 = gc(f.v4);
+  if (tid < ncols + 2 * R) {
+    const int gx = x0 - R + tid;
+    const unsigned x4 = 4u * (unsigned)clampi_s(gx, 0, W - 1), W4 = 4u * (unsigned)W;
+    const bool colin = gx >= 0 && gx < W;
+    // stage 5 reads the top row for rows lo .. top - 1 of the column (none
+    // when the column has no top)
+    const int top = s_top[tid];
+    const int lo = top >= H ? H : (kp.ext_rows > 0 ? max(top - kp.ext_rows, 0) : 0);
+    const unsigned span = (unsigned)(min(top, H) - lo);
+    const int yb = y0 - R;
+    int a[SRM];
+#pragma unroll
+    for (int k = 0; k < SRM; ++k) {
+      const int y = clampi_s(yb + k, 0, H - 1);
+      const int row = (unsigned)(y - lo) < span ? top : y;
+      a[k] = ldk(v4, (unsigned)row * W4 + x4);
+    }
+#pragma unroll
+    for (int k = 0; k < SRM; ++k) a[k] = (colin && (unsigned)(yb + k) < (unsigned)H) ? max(a[k], 0) : 0;
+    if (tid >= R && tid < R + ncols) {
+      unsigned em = 0u;
+#pragma unroll
+      for (int r = 0; r < kBandRows; ++r)
+        if (r < nr && a[R + r] <= kthr) em |= 1u << r;
+      s_em[tid - R] = em;
+      if (em != 0u) atomicOr(s_rows, em);
+    }
+    int o[kBandRows];
+    vhgw31(a, o);
+#pragma unroll
+    for (int r = 0; r < kBandRows; ++r) S[r * kDWV + tid] = o[r];
+  }
+  __syncthreads();
+  // band row rr, columns j0 .. j0 + 31: lanes 0-31 of a wave take rows 0-31
+  // of one run, lanes 32-63 those of the next
+  const unsigned rows = *s_rows;
+  const int rr = tid & 31, j0 = (tid >> 5) * 32;
+  if (j0 < ncols && ((rows >> rr) & 1u)) {
+    int a[62], o[32];
+#pragma unroll
+    for (int c = 0; c < 62; ++c) a[c] = S[rr * kDWV + j0 + c];
+    vhgw31(a, o);
+#pragma unroll
+    for (int c = 0; c < 32; ++c)
+      if (j0 + c < ncols && ((s_em[j0 + c] >> rr) & 1u)) out(y0 + rr, x0 + j0 + c, o[c]);
+  }
+}
+
 // window_max for up to NC cells of one phase-1 tile at once (pos: y * W + x,
 // nc of them valid), every load issued before the first is used; the tops
 // come from s_top, which holds those of columns xs0 .. xs0 + kDW - 1
@@ -1521,11 +1595,16 @@ __device__ __forceinline__ void window_max_n(const FrameDesc& f, const KParams& 
 // follow its first non-empty row; the hole rows within the band are checked
 // cell by cell (all threads over the flattened list of hole-column rows).
 // Up to kFillSparse cells then each take the window max (window_max_n, three
-// per wave at a time); a band with more is filled separably (fill_region).
-__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fill_tiles(FrameSource src, KParams kp, int lth) {
+// per wave at a time); a band with more is filled separably: VF (the 31x31
+// window) by fill_band_vfirst, other windows by fill_region.  The fill is
+// bound by the latency of a band's dependent steps, so VF, whose band needs
+// half the LDS, runs five waves per SIMD (96 registers) rather than four.
+template <bool VF>
+__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(VF ? 5 : 4))) void k_fill_tiles(FrameSource src, KParams kp, int lth) {
   constexpr int SR = kBandRows + 2 * kFillRad;
-  __shared__ int S[SR * kDW];
+  __shared__ int S[VF ? kBandRows * kDWV : SR * kDW];
   __shared__ int s_top[kDW];
+  __shared__ unsigned s_em[VF ? kLocalTW : 1], s_rows;
   __shared__ int s_list[kFillSparse];
   __shared__ short s_hcol[kLocalTW], s_hfirst[kLocalTW];
   __shared__ int s_n, s_lead, s_nh, s_cand;
@@ -1549,17 +1628,21 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     const int b0 = band * kBandRows, b1 = min(b0 + kBandRows, rows);   // the band's rows within the tile
     gcint* v4 = gc(f.v4);
     gint* v4w = gw(f.v4);
+    // tops of the columns x0 - rl .. x0 - rl + kDW - 1 (clamped into the
+    // image) and the band's column records, loaded before the barrier so
+    // that they are in flight while the previous band's last cells go out
+    const int topv = tid < kDW ? (kp.extrapolate ? gc(f.top)[clampi_s(x0 - rl + tid, 0, W - 1)] : H) : 0;
+    const int x = x0 + tid;
+    const int rec = tid < cols ? gc(f.v6p)[(size_t)tr * W + x] : 0;
     __syncthreads();                                   // LDS of the previous band is no longer read
     if (tid == 0) {
       s_n = 0;
       s_lead = 0;
       s_nh = 0;
       s_cand = 0;
+      if constexpr (VF) s_rows = 0u;
     }
-    // tops of the columns x0 - rl .. x0 - rl + kDW - 1 (clamped into the image)
-    if (tid < kDW) s_top[tid] = kp.extrapolate ? gc(f.top)[clampi_s(x0 - rl + tid, 0, W - 1)] : H;
-    const int x = x0 + tid;
-    const int rec = tid < cols ? gc(f.v6p)[(size_t)tr * W + x] : 0;
+    if (tid < kDW) s_top[tid] = topv;
     __syncthreads();
     // this thread's column within the band: leading rows l0 .. l1 - 1 (tile
     // rows), and whether empty rows may follow the first non-empty one
@@ -1614,8 +1697,9 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
       dense = s_n > kFillSparse;
     }
     if (!dense) {
-      // three cells per wave at a time
-      constexpr int NC = 3;
+      // three cells per wave at a time (two in the five-wave build of the
+      // 31x31 window's kernel, which would otherwise spill)
+      constexpr int NC = VF ? 2 : 3;
       const int n = s_n;
       for (int j0 = wv * NC; j0 < n; j0 += NC * (kDenseThreads / kLanes)) {
         const int nc = min(NC, n - j0);
@@ -1630,10 +1714,13 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         }
       }
     } else {
-      fill_region<kBandRows>(f, kp, y0 + b0, b1 - b0, x0, cols, S, s_top, tid,
-                             [&](int y, int xx, int m) {
-                               if (m > 0) v4w[(size_t)y * W + xx] = m | kFillTag;
-                             });
+      // s_top holds the staged columns' tops, and S is not read since the
+      // barrier at the top of the loop
+      auto put = [&](int y, int xx, int m) {
+        if (m > 0) v4w[(size_t)y * W + xx] = m | kFillTag;
+      };
+      if constexpr (VF) fill_band_vfirst(f, kp, y0 + b0, b1 - b0, x0, cols, S, s_top, s_em, &s_rows, tid, put);
+      else fill_region<kBandRows, true>(f, kp, y0 + b0, b1 - b0, x0, cols, S, s_top, tid, put);
     }
   }
 }
@@ -1753,13 +1840,21 @@ hipError_t launch_prefill(const FrameSource& src, const KParams& kp, int local_r
   hipLaunchKernelGGL(k_fill_scan, dim3(scan_grid), dim3(kLanes), 0, s, src, kp, local_rows);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fill_tiles, dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
+  if (prefill_full_window(kp))
+    hipLaunchKernelGGL(k_fill_tiles<true>, dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
+  else
+    hipLaunchKernelGGL(k_fill_tiles<false>, dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
   return hipGetLastError();
 }
 
-int prefill_resident_blocks() {
+bool prefill_full_window(const KParams& kp) { return kp.rl == kFillRad; }
+
+int prefill_resident_blocks(bool full_window) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles, kDenseThreads, 0) != hipSuccess) return 1;
+  const hipError_t e =
+      full_window ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<true>, kDenseThreads, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<false>, kDenseThreads, 0);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
