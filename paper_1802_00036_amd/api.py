@@ -89,10 +89,13 @@ def _release_queue_streams() -> None:
     # profiler's, which has ended in a fault over streams still alive then)
     lib = L.lib()
     for idx, streams in list(_QUEUE_STREAMS.items()):
-        with torch.cuda.device(idx):
-            torch.cuda.synchronize()
-            for s in streams:
-                lib.ipb_stream_destroy(ctypes.c_void_p(s.cuda_stream))
+        try:
+            with torch.cuda.device(idx):
+                torch.cuda.synchronize()
+                for s in streams:
+                    lib.ipb_stream_destroy(ctypes.c_void_p(s.cuda_stream))
+        except RuntimeError:
+            pass        # a device already in error: the runtime's teardown takes them
     _QUEUE_STREAMS.clear()
 
 
