@@ -1491,13 +1491,17 @@ constexpr int kFillScan = 2048;   // hole rows of a band checked one by one; bey
 // out(y, x, value).  The caller has put the staged columns' tops in s_top,
 // set *s_rows to 0 and passed a barrier since; no thread still reads S.
 constexpr int kDWV = 159;   // LDS row pitch: odd, so a row pass's lanes (one row each) hit distinct banks
+// threads of the 31x31 window's band fill: the 138 staged columns and the
+// 128 threads of the row pass fit three waves
+constexpr int kVfThreads = 192;
 template <class Out>
 __device__ __forceinline__ void fill_band_vfirst(const FrameDesc& f, const KParams& kp, int y0, int nr, int x0,
                                                  int ncols, int* S, const int* s_top, unsigned* s_em,
                                                  unsigned* s_rows, int tid, Out&& out) {
   constexpr int R = kFillRad, SRM = kBandRows + 2 * R;
   static_assert(SRM == 62 && kBandRows == 32, "vhgw31 takes 62 values to 32 maxima");
-  static_assert(4 * 32 + 2 * R <= kDWV && kLocalTW <= 128 && kLocalTW + 2 * R <= kDenseThreads, "band layout");
+  static_assert(4 * 32 + 2 * R <= kDWV && kLocalTW <= 128 && kLocalTW + 2 * R <= kVfThreads && kVfThreads >= 128,
+                "band layout");
   const int H = f.H, W = f.W;
   const int kthr = key(kp.thr);
   gcint* v4 = gc(f.v4);
@@ -1594,13 +1598,16 @@ __device__ __forceinline__ void window_max_n(const FrameDesc& f, const KParams& 
 // column records and tops give each column's leading rows and whether holes
 // follow its first non-empty row; the hole rows within the band are checked
 // cell by cell (all threads over the flattened list of hole-column rows).
-// Up to kFillSparse cells then each take the window max (window_max_n, three
-// per wave at a time); a band with more is filled separably: VF (the 31x31
+// Up to kFillSparse cells then each take the window max (window_max_n, two
+// or three per wave at a time); a band with more is filled separably: VF (the 31x31
 // window) by fill_band_vfirst, other windows by fill_region.  The fill is
 // bound by the latency of a band's dependent steps, so VF, whose band needs
-// half the LDS, runs five waves per SIMD (96 registers) rather than four.
+// half the LDS, runs five waves per SIMD (96 registers) rather than four, in
+// workgroups of three waves: six bands per CU.
 template <bool VF>
-__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(VF ? 5 : 4))) void k_fill_tiles(FrameSource src, KParams kp, int lth) {
+__global__ __launch_bounds__(VF ? kVfThreads : kDenseThreads) __attribute__((amdgpu_waves_per_eu(VF ? 5 : 4))) void k_fill_tiles(FrameSource src, KParams kp, int lth) {
+  constexpr int NT = VF ? kVfThreads : kDenseThreads;   // threads of the workgroup
+  static_assert(NT >= kDW && NT >= kLocalTW, "a thread per staged column top and per band column");
   constexpr int SR = kBandRows + 2 * kFillRad;
   __shared__ int S[VF ? kBandRows * kDWV : SR * kDW];
   __shared__ int s_top[kDW];
@@ -1676,11 +1683,11 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(V
       // threads, four per thread at a time; a thread stops once the band has
       // more than kFillSparse cells (it is then filled separably)
       const int nh = s_nh, nb = b1 - b0, total = nh * nb;
-      for (int base = 0; base < total; base += 4 * kDenseThreads) {
+      for (int base = 0; base < total; base += 4 * NT) {
         if (*(volatile int*)&s_n > kFillSparse) break;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int idx = base + u * kDenseThreads + tid;
+          const int idx = base + u * NT + tid;
           if (idx < total) {
             const int k = idx / nb, r = b0 + idx - k * nb;
             const int c = s_hcol[k];
@@ -1701,7 +1708,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(V
       // 31x31 window's kernel, which would otherwise spill)
       constexpr int NC = VF ? 2 : 3;
       const int n = s_n;
-      for (int j0 = wv * NC; j0 < n; j0 += NC * (kDenseThreads / kLanes)) {
+      for (int j0 = wv * NC; j0 < n; j0 += NC * (NT / kLanes)) {
         const int nc = min(NC, n - j0);
         int pos[NC], m[NC];
 #pragma unroll
@@ -1841,7 +1848,7 @@ hipError_t launch_prefill(const FrameSource& src, const KParams& kp, int local_r
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (prefill_full_window(kp))
-    hipLaunchKernelGGL(k_fill_tiles<true>, dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
+    hipLaunchKernelGGL(k_fill_tiles<true>, dim3(tile_grid), dim3(kVfThreads), 0, s, src, kp, local_rows);
   else
     hipLaunchKernelGGL(k_fill_tiles<false>, dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
   return hipGetLastError();
@@ -1852,7 +1859,7 @@ bool prefill_full_window(const KParams& kp) { return kp.rl == kFillRad; }
 int prefill_resident_blocks(bool full_window) {
   int nb = 0;
   const hipError_t e =
-      full_window ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<true>, kDenseThreads, 0)
+      full_window ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<true>, kVfThreads, 0)
                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<false>, kDenseThreads, 0);
   if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
