@@ -24,7 +24,7 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib as L
-from .api import Params, _check_map, _stream_handle, _workspace, frames_array, queue_streams
+from .api import Params, _check_map, _frames_array, _stream_handle, _workspace, queue_streams
 
 Shape = Tuple[int, int]
 # the library's automatic tile rule, in waves (MI355X: 256 CUs x 4 SIMDs)
@@ -153,7 +153,7 @@ class GraphBatch:
         outs = list(outs)
         if not frames or len(frames) > self.max_frames:
             raise ValueError(f"batch of {len(frames)} frames; capacity {self.max_frames}")
-        arr = frames_array(frames, outs)
+        arr, side = _frames_array(frames, outs)
         k = self.turn
         self.turn ^= 1
         if self.done[k] is not None:
@@ -170,7 +170,7 @@ class GraphBatch:
         # the captured launch leaves out the step for frames under 3 rows or
         # columns (planned phase -2); a batch holding such a frame runs
         # eagerly with every step
-        tiny = any(f.shape[0] < 3 or f.shape[1] < 3 for f in frames)
+        tiny = side < 3
         with torch.cuda.stream(self.stream):
             if not self.use_graph or tiny:
                 self._enqueue(k, -1)

@@ -326,3 +326,26 @@ int main() { return check<9>(1) | check<25>(2) | check<13>(3) | check<7>(4); }
             fh.write(src)
         subprocess.run(["g++", "-O1", "-std=c++17", f"-I{CSRC}", cpp, "-o", exe], check=True)
         assert subprocess.run([exe]).returncode == 0
+
+
+def test_frame_array_layout_and_packing(monkeypatch):
+    """The batch's ipb_frame array is written in one copy from (input
+    pointer, output pointer, H | W << 32) per frame: that is the struct's
+    layout, and every field reads back as set (CPU tensors stand in for
+    device maps, whose check is replaced)."""
+    import torch
+    from paper_1802_00036_amd import api
+    assert ctypes.sizeof(L.CFrame) == 24
+    assert (L.CFrame.in_.offset, L.CFrame.out.offset, L.CFrame.H.offset, L.CFrame.W.offset) == (0, 8, 16, 20)
+    monkeypatch.setattr(api, "_is_map", lambda t: True)
+    shapes = [(375, 1242), (3, 5), (1, 7), (1024, 4096)]
+    ins = [torch.empty(H, W) for H, W in shapes]
+    outs = [torch.empty(H, W) for H, W in shapes]
+    arr, side = api._frames_array(ins, outs)
+    assert side == 1
+    for i, (H, W) in enumerate(shapes):
+        assert (arr[i].in_, arr[i].out, arr[i].H, arr[i].W) == (ins[i].data_ptr(), outs[i].data_ptr(), H, W)
+    with pytest.raises(ValueError):
+        api._frames_array(ins, outs[:-1])
+    with pytest.raises(ValueError):
+        api._frames_array(ins[:1], [torch.empty(375, 1241)])
