@@ -318,6 +318,10 @@ void build_plan(const ipb_frame* frames, int n, const Resolved& r, void* ws, voi
   hdr->slow_cap = (int32_t)gtot;
   hdr->ltab = ltab;
   hdr->gtab = gtab;
+  bool same = frames[0].H >= 3 && frames[0].W >= 3;
+  for (int i = 1; i < n && same; ++i) same = frames[i].H == frames[0].H && frames[i].W == frames[0].W;
+  hdr->g_rows_same = same ? cdiv(frames[0].H, r.gth) : 0;
+  hdr->g_cols_same = same ? cdiv(frames[0].W, r.gtw) : 0;
 }
 
 size_t batch_bytes(const ipb_frame* frames, int n, const Resolved& r) {

@@ -53,7 +53,11 @@ struct PlanHeader {
   int32_t pad0;
   int32_t* ltab;              // frame index of every phase-1 tile (written by k_reset)
   int32_t* gtab;              // frame index of every phase-2 tile (written by k_reset)
-  int32_t pad1[14];
+  // phase-2 tile rows and columns of every frame when all frames have one
+  // shape of at least 3 x 3 (else 0): k_global_rows then visits the tiles
+  // bottom tile row first, over all frames
+  int32_t g_rows_same, g_cols_same;
+  int32_t pad1[12];
 };
 static_assert(sizeof(PlanHeader) == 128, "plan header layout");
 static_assert(sizeof(FrameDesc) == 64, "frame descriptor layout");

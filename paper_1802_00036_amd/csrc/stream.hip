@@ -1107,12 +1107,32 @@ __global__ __launch_bounds__(kLanes * kLocalWaves) __attribute__((amdgpu_waves_p
   const int total = src.plan ? src.plan->gtiles : src.single_gtiles;
   int32_t* slow = src.plan ? src.plan->slow : src.slow;
   const int cap = src.plan ? src.plan->slow_cap : src.slow_cap;
-  for (int t = xcd_tile_s(blockIdx.x, gridDim.x) * kLocalWaves + wave; t < total; t += gridDim.x * kLocalWaves) {
-    FrameDesc f = src.plan ? plan_frame(src, gc(src.plan->gtab)[t]) : src.single;
-    f = uniform_frame(f);
-    const int gt = t - f.gtile0;
-    const int tr = gt / f.gcols;
-    const int ty0 = tr * TH, tx0 = (gt - tr * f.gcols) * kGlobalTW;
+  // A batch of frames of one shape is visited bottom tile row first, over
+  // all frames, its workgroups going to the XCDs in turn: the top tile rows
+  // lie above the column tops, where a tile only copies the sky row's
+  // outputs, so the last tiles handed out, which run while the SIMDs empty,
+  // are cheap ones on every XCD.  Other launches go frame by frame, each
+  // XCD taking a contiguous run of tiles.
+  const int grows = src.plan ? src.plan->g_rows_same : 0;
+  const int gcols = src.plan ? src.plan->g_cols_same : 0;
+  const int b0 = grows ? (int)blockIdx.x : xcd_tile_s(blockIdx.x, gridDim.x);
+  for (int t = b0 * kLocalWaves + wave; t < total; t += gridDim.x * kLocalWaves) {
+    FrameDesc f;
+    int tr, tc;
+    if (grows) {
+      const int per_row = src.plan->n * gcols;        // tiles of one tile row over all frames
+      const int k = t / per_row, rem = t - k * per_row;
+      const int fi = rem / gcols;
+      f = uniform_frame(plan_frame(src, fi));
+      tr = grows - 1 - k;
+      tc = rem - fi * gcols;
+    } else {
+      f = uniform_frame(src.plan ? plan_frame(src, gc(src.plan->gtab)[t]) : src.single);
+      const int gt = t - f.gtile0;
+      tr = gt / f.gcols;
+      tc = gt - tr * f.gcols;
+    }
+    const int ty0 = tr * TH, tx0 = tc * kGlobalTW;
     if (f.H < 3 || f.W < 3) {
       if (lane == 0) {
         const int pos = atomic_add_g(slow + 1, 1);

@@ -4,6 +4,7 @@
 // the offset and size arithmetic, on random and boundary inputs.  Every call
 // here returns before any HIP call is made.  Exit status 0 when every check
 // holds; a sanitizer report aborts the run.
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -137,6 +138,13 @@ void plans(std::mt19937& rng) {
     const int n = 1 + (int)(rng() % 70);
     const bool in_place = (it % 3) == 0;
     std::vector<ipb_frame> f = random_frames(rng, n, in_place);
+    if (it % 4 == 1) {
+      // a batch of one shape: the smallest height and width of the frames
+      // (every buffer still holds its frame)
+      int h = f[0].H, w = f[0].W;
+      for (const ipb_frame& x : f) h = std::min(h, x.H), w = std::min(w, x.W);
+      for (ipb_frame& x : f) x.H = h, x.W = w;
+    }
     ipb_params q = p;
     q.tile_local = (int)(rng() % 10);
     q.tile_global = (int)(rng() % 8);
@@ -176,6 +184,15 @@ void plans(std::mt19937& rng) {
       CHECK(((uintptr_t)v4 % 256) == 0 && ((uintptr_t)v6 % 256) == 0);
     }
     CHECK(cols == sum_w && lt == lsum && gt == gsum);
+    // frames of one shape (at least 3 x 3) give phase 2's per-frame tiling
+    bool same = f[0].H >= 3 && f[0].W >= 3;
+    for (int i = 1; i < n; ++i) same = same && f[i].H == f[0].H && f[i].W == f[0].W;
+    if (same) {
+      CHECK(hdr->g_rows_same == (f[0].H + hdr->gt_rows - 1) / hdr->gt_rows && hdr->g_cols_same == d[0].gcols);
+      CHECK((long long)hdr->g_rows_same * hdr->g_cols_same * n == gt);
+    } else {
+      CHECK(hdr->g_rows_same == 0 && hdr->g_cols_same == 0);
+    }
   }
 }
 
