@@ -401,6 +401,25 @@ def test_queue_streams_have_queues_of_their_own():
     assert three < 2.0 * one
 
 
+@pytest.mark.parametrize("shape,n,tiles", [((375, 1242), 5, (10, 5)), ((3, 3), 4, (0, 0)), ((130, 301), 7, (5, 6)),
+                                            ((64, 120), 9, (10, 7)), ((1024, 250), 3, (6, 7)), ((17, 4096), 2, (7, 8)),
+                                            ((200, 640), 6, (8, 9))])
+def test_batch_of_one_shape_equals_alone(shape, n, tiles):
+    """A batch whose frames share one shape takes phase 2's tiles bottom tile
+    row first over all frames (from the plan's shared tiling): every output
+    bitwise equal to the frame completed alone, for frames of one tile and
+    of many, odd widths, the 3 x 3 minimum and each phase-2 tile height of
+    the default chain (64, 32, 128, 16 and 8 rows)."""
+    H, W = shape
+    frames = [lidar(H, W, [53, H, i]) for i in range(n)]
+    p = dataclasses.replace(api.Params(), tile_local=tiles[0], tile_global=tiles[1])
+    print(f"[one shape] {n} x {H}x{W}, tiles {tiles}", flush=True)
+    outs = api.complete_batch(frames, p)
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(frames, outs)):
+        assert np.array_equal(bits(o), bits(api.complete(f))), f"frame {i}"
+
+
 @pytest.mark.parametrize("kind", ["pool", "queue"])
 def test_batches_in_flight_on_streams(kind):
     """Three batches in flight on three streams (torch's pool streams, or
