@@ -10,6 +10,7 @@ import array
 import atexit
 import ctypes
 import dataclasses
+import warnings
 from typing import List, Optional, Sequence
 
 import torch
@@ -94,13 +95,14 @@ def _release_queue_streams() -> None:
             with torch.cuda.device(idx):
                 torch.cuda.synchronize()
                 for s in streams:
-                    lib.ipb_stream_destroy(ctypes.c_void_p(s.cuda_stream))
+                    if isinstance(s, torch.cuda.ExternalStream):
+                        lib.ipb_stream_destroy(ctypes.c_void_p(s.cuda_stream))
         except RuntimeError:
             pass        # a device already in error: the runtime's teardown takes them
     _QUEUE_STREAMS.clear()
 
 
-def queue_streams(n: int, device=None) -> List[torch.cuda.ExternalStream]:
+def queue_streams(n: int, device=None) -> List[torch.cuda.Stream]:
     """`n` streams of `device` (default: the current one), each on a
     hardware queue of its own (ipb_stream_create), for batches kept in
     flight side by side.  Streams from torch's pool share the runtime's few
@@ -109,7 +111,8 @@ def queue_streams(n: int, device=None) -> List[torch.cuda.ExternalStream]:
     device and live until the interpreter exits; every caller that asks for `n`
     gets the first `n` of them, so independent users of one process share
     them.  They synchronise with the legacy null stream, as any stream
-    created without flags does."""
+    created without flags does.  Should the runtime refuse such a stream,
+    a warning says so and torch's pool streams stand in."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     idx = dev.index if dev.index is not None else torch.cuda.current_device()
     if not _QUEUE_STREAMS:
@@ -119,7 +122,15 @@ def queue_streams(n: int, device=None) -> List[torch.cuda.ExternalStream]:
     with torch.cuda.device(idx):
         while len(have) < n:
             h = ctypes.c_void_p()
-            L.check(lib.ipb_stream_create(ctypes.byref(h)), "ipb_stream_create")
+            st = lib.ipb_stream_create(ctypes.byref(h))
+            if st == L.IPB_ERR_HIP:
+                # a runtime that refuses compute-unit masks: torch's pool
+                # streams, which may share hardware queues
+                warnings.warn(f"ipb_stream_create: {L.status_string(st)} (hipError "
+                              f"{lib.ipb_last_hip_error()}); using torch's pool streams", RuntimeWarning)
+                have.append(torch.cuda.Stream(device=torch.device("cuda", idx)))
+                continue
+            L.check(st, "ipb_stream_create")
             have.append(torch.cuda.ExternalStream(h.value, device=torch.device("cuda", idx)))
     return have[:n]
 
