@@ -401,6 +401,30 @@ def test_queue_streams_have_queues_of_their_own():
     assert three < 2.0 * one
 
 
+def test_queue_streams_fall_back_to_pool_streams(monkeypatch):
+    """A runtime that refuses a compute-unit-masked stream: queue_streams
+    warns and hands out torch's pool streams, on which a batch still
+    completes bitwise as the frame alone."""
+    lib = L.lib()
+    calls = []
+
+    def refuse(ptr):
+        calls.append(ptr)
+        return L.IPB_ERR_HIP
+
+    monkeypatch.setattr(api, "_QUEUE_STREAMS", {})
+    monkeypatch.setattr(lib, "ipb_stream_create", refuse)
+    with pytest.warns(RuntimeWarning, match="pool streams"):
+        qs = api.queue_streams(2)
+    assert len(calls) == 2 and all(not isinstance(s, torch.cuda.ExternalStream) for s in qs)
+    f = lidar(200, 640, [61])
+    torch.cuda.synchronize()
+    with torch.cuda.stream(qs[1]):
+        out = api.complete_batch([f])[0]
+    qs[1].synchronize()
+    assert np.array_equal(bits(out), bits(api.complete(f)))
+
+
 @pytest.mark.parametrize("shape,n,tiles", [((375, 1242), 5, (10, 5)), ((3, 3), 4, (0, 0)), ((130, 301), 7, (5, 6)),
                                             ((64, 120), 9, (10, 7)), ((1024, 250), 3, (6, 7)), ((17, 4096), 2, (7, 8)),
                                             ((200, 640), 6, (8, 9))])
