@@ -435,9 +435,14 @@ int launch_phases(const FrameSource& src, const Resolved& r, int phase, int last
   if (last_stage < 5) return IPB_OK;
   if ((phase == -1 || phase == 2) && prefill) {
     // one scanning wave per phase-1 tile (those of the first tile row work);
-    // one workgroup per queued band, at most the resident ones
-    const int tgrid = std::max(1, (int)std::min<long long>((long long)kBandsPerTile * max_lt, prefill_res(dev, kp) * cus));
-    e = launch_prefill(src, kp, r.lth, max_lt, tgrid, s);
+    // one workgroup per queued band, at most the resident ones.  When every
+    // band of every tile fits one round of resident workgroups, the fill
+    // visits them all and the scan is left out.
+    const long long slots = (long long)prefill_res(dev, kp) * cus;
+    const long long bands = (long long)cdiv(r.lth, kBandRows) * max_lt;
+    const bool all_bands = bands <= slots;
+    const int tgrid = std::max(1, (int)std::min<long long>(all_bands ? bands : (long long)kBandsPerTile * max_lt, slots));
+    e = launch_prefill(src, kp, r.lth, max_lt, tgrid, all_bands, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   if (phase == -1 || phase == 3) {

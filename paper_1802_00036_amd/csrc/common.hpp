@@ -128,6 +128,7 @@ struct FrameSource {
 // runs before phase 2.
 constexpr int kCellEmpty = 32;
 constexpr int kQueueHead = 8;
+constexpr int kBandRows = 32;      // rows of a band of the fill ahead of phase 2
 constexpr int kBandsPerTile = 4;   // 32-row bands of a phase-1 tile (at most 128 rows)
 __host__ __device__ inline size_t slow_queue_ints(int gcap, int lcap) {
   return kQueueHead + (17 + 8 * kCellEmpty) * (size_t)gcap + 2 * kBandsPerTile * (size_t)lcap;
@@ -167,7 +168,7 @@ hipError_t launch_global_stream(const FrameSource& src, const KParams& kp, int t
 hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int tile_id, int grid, int cell_grid,
                                 hipStream_t s);
 hipError_t launch_prefill(const FrameSource& src, const KParams& kp, int local_rows, int scan_grid, int tile_grid,
-                          hipStream_t s);
+                          bool all_bands, hipStream_t s);
 bool fast_chain(const KParams& kp);
 // whether the fill ahead of phase 2 takes the 31x31 window's kernel, and
 // the resident workgroups per CU of the kernel it takes

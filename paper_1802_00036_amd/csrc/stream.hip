@@ -1408,7 +1408,6 @@ __global__ __launch_bounds__(kDenseThreads) void k_fill_dense(FrameSource src, K
 // one phase-1 tile, whose workgroup alone writes it.
 
 // bits of the bands (kBandRows rows) that rows lo .. hi of a tile touch
-constexpr int kBandRows = 32;
 __device__ __forceinline__ unsigned band_bits(int lo, int hi) {
   return (2u << (hi / kBandRows)) - (1u << (lo / kBandRows));
 }
@@ -1623,8 +1622,12 @@ __device__ __forceinline__ void window_max_n(const FrameDesc& f, const KParams& 
 // window) by fill_band_vfirst, other windows by fill_region.  The fill is
 // bound by the latency of a band's dependent steps, so VF, whose band needs
 // half the LDS, runs five waves per SIMD (96 registers) rather than four, in
-// workgroups of three waves: six bands per CU.
-template <bool VF>
+// workgroups of three waves: six bands per CU.  ALL: the launch
+// visits every band of every phase-1 tile rather than those k_fill_scan
+// queued (small launches, whose bands all fit one round of workgroups: the
+// classification above finds the same cells, and the scan would cost a
+// launch and a round trip more than the bands it spares).
+template <bool VF, bool ALL>
 __global__ __launch_bounds__(VF ? kVfThreads : kDenseThreads) __attribute__((amdgpu_waves_per_eu(VF ? 5 : 4))) void k_fill_tiles(FrameSource src, KParams kp, int lth) {
   constexpr int NT = VF ? kVfThreads : kDenseThreads;   // threads of the workgroup
   static_assert(NT >= kDW && NT >= kLocalTW, "a thread per staged column top and per band column");
@@ -1639,13 +1642,23 @@ __global__ __launch_bounds__(VF ? kVfThreads : kDenseThreads) __attribute__((amd
   gcint* slow = gc(src.plan ? src.plan->slow : src.slow);
   const int gcap = src.plan ? src.plan->slow_cap : src.slow_cap;
   const int lcap = src.plan ? src.plan->ltiles : src.single_ltiles;
-  const int count = min(slow[4], kBandsPerTile * lcap);
+  const int nbt = (lth + kBandRows - 1) / kBandRows;    // bands per phase-1 tile
+  const int count = ALL ? nbt * lcap : min(slow[4], kBandsPerTile * lcap);
   gcint* queue = slow + fill_queue_offset(gcap);
   const int kthr = key(kp.thr);
   const int rl = kp.rl;
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
-    const int t = queue[2 * i], e1 = queue[2 * i + 1];
-    const int fidx = e1 & 0xffffff, band = (unsigned)e1 >> 24;
+    int t, fidx, band;
+    if constexpr (ALL) {
+      t = i / nbt;
+      band = i - t * nbt;
+      fidx = src.plan ? gc(src.plan->ltab)[t] : 0;
+    } else {
+      t = queue[2 * i];
+      const int e1 = queue[2 * i + 1];
+      fidx = e1 & 0xffffff;
+      band = (int)((unsigned)e1 >> 24);
+    }
     FrameDesc f = src.plan ? plan_frame(src, fidx) : src.single;
     f = uniform_frame(f);
     const int H = f.H, W = f.W;
@@ -1653,6 +1666,10 @@ __global__ __launch_bounds__(VF ? kVfThreads : kDenseThreads) __attribute__((amd
     const int y0 = tr * lth, x0 = tc * kLocalTW;
     const int rows = min(lth, H - y0), cols = min(kLocalTW, W - x0);
     const int b0 = band * kBandRows, b1 = min(b0 + kBandRows, rows);   // the band's rows within the tile
+    // (whole workgroup alike, ahead of the band's first barrier) frames
+    // under 3 rows or columns are left to phase 2, as the scan leaves them;
+    // a tile's last bands may lie past its rows
+    if (ALL && (H < 3 || W < 3 || b0 >= rows)) continue;
     gcint* v4 = gc(f.v4);
     gint* v4w = gw(f.v4);
     // tops of the columns x0 - rl .. x0 - rl + kDW - 1 (clamped into the
@@ -1863,14 +1880,21 @@ hipError_t launch_global_repair(const FrameSource& src, const KParams& kp, int t
 }
 
 hipError_t launch_prefill(const FrameSource& src, const KParams& kp, int local_rows, int scan_grid, int tile_grid,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_scan, dim3(scan_grid), dim3(kLanes), 0, s, src, kp, local_rows);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (prefill_full_window(kp))
-    hipLaunchKernelGGL(k_fill_tiles<true>, dim3(tile_grid), dim3(kVfThreads), 0, s, src, kp, local_rows);
+                          bool all_bands, hipStream_t s) {
+  if (!all_bands) {
+    hipLaunchKernelGGL(k_fill_scan, dim3(scan_grid), dim3(kLanes), 0, s, src, kp, local_rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const bool vf = prefill_full_window(kp);
+  if (vf && all_bands)
+    hipLaunchKernelGGL((k_fill_tiles<true, true>), dim3(tile_grid), dim3(kVfThreads), 0, s, src, kp, local_rows);
+  else if (vf)
+    hipLaunchKernelGGL((k_fill_tiles<true, false>), dim3(tile_grid), dim3(kVfThreads), 0, s, src, kp, local_rows);
+  else if (all_bands)
+    hipLaunchKernelGGL((k_fill_tiles<false, true>), dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
   else
-    hipLaunchKernelGGL(k_fill_tiles<false>, dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
+    hipLaunchKernelGGL((k_fill_tiles<false, false>), dim3(tile_grid), dim3(kDenseThreads), 0, s, src, kp, local_rows);
   return hipGetLastError();
 }
 
@@ -1879,8 +1903,8 @@ bool prefill_full_window(const KParams& kp) { return kp.rl == kFillRad; }
 int prefill_resident_blocks(bool full_window) {
   int nb = 0;
   const hipError_t e =
-      full_window ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<true>, kVfThreads, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<false>, kDenseThreads, 0);
+      full_window ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<true, false>, kVfThreads, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fill_tiles<false, false>, kDenseThreads, 0);
   if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
